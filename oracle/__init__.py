@@ -1,0 +1,42 @@
+"""FP64 CPU oracle for the hyperbolic self-gravity hot path -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import, call, link or execute anything in this package.  The
+HIP library never does, and this package never imports the HIP library: the two
+share no code.  The only module both sides use is ``workloads`` (seeded input
+generators, none of the method's arithmetic).
+
+What each part follows (paper: Hirai, Nagakura, Okawa & Fujisawa,
+arXiv:1602.05700), and what pins it (tests/test_oracle_pins.py):
+
+* ``hgs_oracle.c: orc_substeps`` -- explicit leapfrog of the inhomogeneous wave
+  equation, Eq. (2), rho frozen over the sub-cycled steps (Sec. 2).  Optional
+  damping eta (an extension, eta = 0 is Eq. (2)).  Pinned by: the closed-form
+  amplitude of a single Dirichlet eigenmode (eta = 0 and eta > 0), the
+  stability limit c dt/dx = 1/sqrt(3), the discrete Poisson solution (DST-I and
+  dense LU) being a fixed point, exact conservation of the discrete energy at
+  eta = 0, exactness on quadratic potentials, linearity in rho.
+* ``orc_moments`` / ``orc_boundary`` -- Dirichlet outer boundary from a
+  multipole expansion of rho (Sec. 2 and Sec. 4, Table I footnote c).  Pinned
+  by: the Legendre addition theorem evaluated by brute force over cells,
+  scipy's spherical harmonics, the monopole -G M / r, and convergence toward
+  the free-space direct sum as lmax grows.
+* ``orc_laplacian`` / ``orc_residual`` -- the steady state Eq. (1) in discrete
+  form.  Pinned by: the discrete Gauss law (telescoping flux), R_b = 1 at a
+  zero state, the DST-I solution giving round-off residuals, second-order
+  convergence toward the closed-form Gaussian potential.
+* ``orc_gradient`` -- g = -grad phi by central differences (the paper is silent
+  on the discretisation).  Pinned by exactness on quadratics and second-order
+  convergence on the Gaussian.
+* ``poisson.py`` -- discrete Dirichlet Poisson solve by DST-I, the limit the
+  method converges to (Eq. (1)); pinned by a dense LU solve on small grids.
+* ``analytic.py`` -- closed forms (uniform sphere, Gaussian, cube self
+  potential) and brute-force sums used as pins.
+* ``nn.py`` -- FP64 3D convolution network pieces (forward and backward) for the
+  learned warm start; pinned by central finite differences.
+
+Parity unpinned: none of the paper's own numerical results can be compared,
+because the paper prints no worked example, table of potentials or figure data
+(all figures are placeholders in the source text).
+"""
+from .core import Grid, Oracle, lib  # noqa: F401

@@ -1,0 +1,361 @@
+/*
+ * Oracle core -- TEST INFRASTRUCTURE, not part of the product.
+ *
+ * A plain, slow, obviously correct FP64 CPU implementation of what the
+ * hyperbolic self-gravity hot path computes (Hirai, Nagakura, Okawa &
+ * Fujisawa, "Hyperbolic Self-Gravity Solver for Large Scale Hydrodynamical
+ * Simulations", arXiv:1602.05700).  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code with
+ * the HIP library: no header, no table, no helper.
+ *
+ * Grid convention (the paper fixes none; the readings are listed in the design
+ * notes): cell-centred uniform grid, interior cell (i,j,k) sits at
+ * x0+(i+1/2)dx, y0+(j+1/2)dx, z0+(k+1/2)dx.  One ghost layer lies one cell
+ * outside each face.  The oracle keeps every 3D field in its own padded
+ * array of shape (nz+2, ny+2, nx+2), x fastest; interior cell (i,j,k) lives
+ * at padded index ((k+1)*(ny+2)+(j+1))*(nx+2)+(i+1).  Edge and corner cells
+ * of the padding are never read.
+ *
+ * Functions:
+ *   orc_moments    multipole moments of rho (Sec. 2 / Sec. 4: Dirichlet
+ *                  boundary "by multipole expansion"), complex orthonormal
+ *                  Y_lm written out from the textbook definition.
+ *   orc_boundary   ghost values phi_b = -G sum_lm 4pi/(2l+1) Q_lm Y_lm / r^(l+1).
+ *   orc_substeps   explicit leapfrog time stepping of Eq. (2), optionally with a
+ *                  damping term eta*dphi/dt (an extension; eta = 0 is Eq. (2)).
+ *   orc_laplacian  the 7-point Laplacian with ghosts, L_h phi.
+ *   orc_gradient   g = -grad phi by central differences.
+ *   orc_residual   residual norms of L_h phi = 4 pi G rho.
+ *
+ * Parity status of every function is listed in oracle/__init__.py.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+static inline size_t pidx(int nx, int ny, int i, int j, int k) {
+    /* padded index of cell (i,j,k); i,j,k may be -1 or n (ghosts) */
+    return ((size_t)(k + 1) * (size_t)(ny + 2) + (size_t)(j + 1)) * (size_t)(nx + 2) + (size_t)(i + 1);
+}
+
+/* ---------------------------------------------------------------------------
+ * Spherical harmonics, textbook definition (Condon-Shortley phase):
+ *   Y_lm(theta,phi) = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) P_l^m(cos theta) e^{i m phi},  m >= 0
+ *   Y_l,-m = (-1)^m conj(Y_lm)
+ * P_l^m from P_m^m = (-1)^m (2m-1)!! (1-x^2)^{m/2},  P_{m+1}^m = x (2m+1) P_m^m,
+ * (l-m) P_l^m = x (2l-1) P_{l-1}^m - (l+m-1) P_{l-2}^m.
+ * Output index: l*l + (m+l), m = -l..l.
+ * ------------------------------------------------------------------------- */
+static double factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return f;
+}
+
+static double assoc_legendre(int l, int m, double x) {
+    /* m >= 0, l >= m */
+    double pmm = 1.0;
+    double s = sqrt(fmax(0.0, 1.0 - x * x));
+    for (int i = 1; i <= m; ++i) pmm *= -(2.0 * i - 1.0) * s;
+    if (l == m) return pmm;
+    double pm1 = x * (2.0 * m + 1.0) * pmm;
+    if (l == m + 1) return pm1;
+    double pl = 0.0;
+    for (int ll = m + 2; ll <= l; ++ll) {
+        pl = (x * (2.0 * ll - 1.0) * pm1 - (ll + m - 1.0) * pmm) / (double)(ll - m);
+        pmm = pm1;
+        pm1 = pl;
+    }
+    return pl;
+}
+
+/* all Y_lm for l <= lmax at direction (cos theta, phi) */
+static void ylm_all(int lmax, double ct, double ph, double* re, double* im) {
+    for (int l = 0; l <= lmax; ++l) {
+        for (int m = 0; m <= l; ++m) {
+            double norm = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - m) / factorial(l + m));
+            double p = assoc_legendre(l, m, ct);
+            double yr = norm * p * cos(m * ph);
+            double yi = norm * p * sin(m * ph);
+            re[l * l + l + m] = yr;
+            im[l * l + l + m] = yi;
+            if (m > 0) {
+                double sg = (m % 2) ? -1.0 : 1.0;
+                re[l * l + l - m] = sg * yr;
+                im[l * l + l - m] = -sg * yi;
+            }
+        }
+    }
+}
+
+/* Spherical coordinates of x about the origin.  At r = 0 the direction is
+ * taken as the +z axis (only r^0 Y_00 survives there). */
+static void to_spherical(double x, double y, double z, double* r, double* ct, double* ph) {
+    *r = sqrt(x * x + y * y + z * z);
+    if (*r > 0.0) {
+        *ct = z / *r;
+        *ph = atan2(y, x);
+    } else {
+        *ct = 1.0;
+        *ph = 0.0;
+    }
+}
+
+/* Q_lm = sum over interior cells of rho dx^3 r^l conj(Y_lm(theta, phi)),
+ * positions relative to origin[3].  rho is COMPACT (nz, ny, nx), x fastest. */
+void orc_moments(int nx, int ny, int nz, double x0, double y0, double z0, double dx,
+                 const double* origin, int lmax, const double* rho,
+                 double* q_re, double* q_im) {
+    int nq = (lmax + 1) * (lmax + 1);
+    double dv = dx * dx * dx;
+    /* one partial sum per z-plane, added up in plane order afterwards */
+    double* part = (double*)calloc((size_t)nz * 2 * nq, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k) {
+        double zr[25], zi[25];
+        double* acc_re = part + (size_t)k * 2 * nq;
+        double* acc_im = acc_re + nq;
+        for (int j = 0; j < ny; ++j) {
+            for (int i = 0; i < nx; ++i) {
+                double m = rho[((size_t)k * ny + j) * nx + i] * dv;
+                if (m == 0.0) continue;
+                double x = x0 + (i + 0.5) * dx - origin[0];
+                double y = y0 + (j + 0.5) * dx - origin[1];
+                double z = z0 + (k + 0.5) * dx - origin[2];
+                double r, ct, ph;
+                to_spherical(x, y, z, &r, &ct, &ph);
+                ylm_all(lmax, ct, ph, zr, zi);
+                double rl = 1.0;
+                for (int l = 0; l <= lmax; ++l) {
+                    for (int mm = -l; mm <= l; ++mm) {
+                        int q = l * l + l + mm;
+                        acc_re[q] += m * rl * zr[q];
+                        acc_im[q] -= m * rl * zi[q]; /* conjugate */
+                    }
+                    rl *= r;
+                }
+            }
+        }
+    }
+    for (int q = 0; q < nq; ++q) { q_re[q] = 0.0; q_im[q] = 0.0; }
+    for (int k = 0; k < nz; ++k)
+        for (int q = 0; q < nq; ++q) {
+            q_re[q] += part[(size_t)k * 2 * nq + q];
+            q_im[q] += part[(size_t)k * 2 * nq + nq + q];
+        }
+    free(part);
+}
+
+/* Multipole potential at one point outside the mass. */
+static double multipole_phi(int lmax, double G, const double* q_re, const double* q_im,
+                            double x, double y, double z) {
+    double r, ct, ph;
+    double yr[25], yi[25];
+    to_spherical(x, y, z, &r, &ct, &ph);
+    ylm_all(lmax, ct, ph, yr, yi);
+    double sum = 0.0;
+    double rinv = 1.0 / r;
+    double rpow = rinv; /* 1/r^(l+1) */
+    for (int l = 0; l <= lmax; ++l) {
+        double pref = 4.0 * M_PI / (2.0 * l + 1.0);
+        for (int mm = -l; mm <= l; ++mm) {
+            int q = l * l + l + mm;
+            /* real part of Q_lm * Y_lm */
+            sum += pref * (q_re[q] * yr[q] - q_im[q] * yi[q]) * rpow;
+        }
+        rpow *= rinv;
+    }
+    return -G * sum;
+}
+
+/* Fill the six ghost faces of the padded array phi with the multipole
+ * potential (one layer outside each face, at ghost-cell centres). */
+void orc_boundary(int nx, int ny, int nz, double x0, double y0, double z0, double dx,
+                  const double* origin, int lmax, double G,
+                  const double* q_re, const double* q_im, double* phi) {
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            double y = y0 + (j + 0.5) * dx - origin[1];
+            double z = z0 + (k + 0.5) * dx - origin[2];
+            phi[pidx(nx, ny, -1, j, k)] = multipole_phi(lmax, G, q_re, q_im, x0 - 0.5 * dx - origin[0], y, z);
+            phi[pidx(nx, ny, nx, j, k)] = multipole_phi(lmax, G, q_re, q_im, x0 + (nx + 0.5) * dx - origin[0], y, z);
+        }
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) {
+            double x = x0 + (i + 0.5) * dx - origin[0];
+            double z = z0 + (k + 0.5) * dx - origin[2];
+            phi[pidx(nx, ny, i, -1, k)] = multipole_phi(lmax, G, q_re, q_im, x, y0 - 0.5 * dx - origin[1], z);
+            phi[pidx(nx, ny, i, ny, k)] = multipole_phi(lmax, G, q_re, q_im, x, y0 + (ny + 0.5) * dx - origin[1], z);
+        }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double x = x0 + (i + 0.5) * dx - origin[0];
+            double y = y0 + (j + 0.5) * dx - origin[1];
+            phi[pidx(nx, ny, i, j, -1)] = multipole_phi(lmax, G, q_re, q_im, x, y, z0 - 0.5 * dx - origin[2]);
+            phi[pidx(nx, ny, i, j, nz)] = multipole_phi(lmax, G, q_re, q_im, x, y, z0 + (nz + 0.5) * dx - origin[2]);
+        }
+}
+
+/* L_h phi at interior cells: (sum of the six neighbours - 6 phi) / dx^2,
+ * neighbours outside the interior being ghosts.  out is COMPACT. */
+void orc_laplacian(int nx, int ny, int nz, double dx, const double* phi, double* out) {
+    double idx2 = 1.0 / (dx * dx);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double c = phi[pidx(nx, ny, i, j, k)];
+                double nb = phi[pidx(nx, ny, i - 1, j, k)] + phi[pidx(nx, ny, i + 1, j, k)]
+                          + phi[pidx(nx, ny, i, j - 1, k)] + phi[pidx(nx, ny, i, j + 1, k)]
+                          + phi[pidx(nx, ny, i, j, k - 1)] + phi[pidx(nx, ny, i, j, k + 1)];
+                out[((size_t)k * ny + j) * nx + i] = (nb - 6.0 * c) * idx2;
+            }
+}
+
+/* copy the six ghost faces of src into dst (padded layout) */
+static void copy_ghosts(int nx, int ny, int nz, const double* src, double* dst) {
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            dst[pidx(nx, ny, -1, j, k)] = src[pidx(nx, ny, -1, j, k)];
+            dst[pidx(nx, ny, nx, j, k)] = src[pidx(nx, ny, nx, j, k)];
+        }
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) {
+            dst[pidx(nx, ny, i, -1, k)] = src[pidx(nx, ny, i, -1, k)];
+            dst[pidx(nx, ny, i, ny, k)] = src[pidx(nx, ny, i, ny, k)];
+        }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            dst[pidx(nx, ny, i, j, -1)] = src[pidx(nx, ny, i, j, -1)];
+            dst[pidx(nx, ny, i, j, nz)] = src[pidx(nx, ny, i, j, nz)];
+        }
+}
+
+static inline double round_storage(double v, int f32) {
+    return f32 ? (double)(float)v : v;
+}
+
+/* nsub explicit substeps of Eq. (2), rho frozen (Sec. 2: the wave equation is
+ * sub-cycled within one hydrodynamical step):
+ *   (phi^{n+1} - 2 phi^n + phi^{n-1}) / dt^2 + eta (phi^{n+1} - phi^{n-1}) / (2 dt)
+ *       = c^2 (L_h phi^n - 4 pi G rho)
+ * solved for phi^{n+1}.  eta = 0 is the paper's equation.
+ * phi_n / phi_nm1: padded arrays, in/out; their ghost values are the frozen
+ * boundary: the ghosts of phi_n are used and copied into phi_nm1.  rho: COMPACT.  If f32 != 0 every new
+ * level is rounded to binary32 (emulates FP32 storage; arithmetic stays FP64). */
+void orc_substeps(int nx, int ny, int nz, double dx, double* phi_n, double* phi_nm1,
+                  const double* rho, double c, double dt, double eta, double G, int nsub, int f32) {
+    size_t np = (size_t)(nx + 2) * (ny + 2) * (nz + 2);
+    double* cur = phi_n;
+    double* old = phi_nm1;
+    double* nxt = (double*)malloc(np * sizeof(double));
+    double* spare = nxt;
+    copy_ghosts(nx, ny, nz, phi_n, phi_nm1);
+    memcpy(nxt, phi_n, np * sizeof(double)); /* carries the ghosts */
+    double a = 0.5 * eta * dt;
+    double c2dt2 = c * c * dt * dt;
+    double idx2 = 1.0 / (dx * dx);
+    for (int n = 0; n < nsub; ++n) {
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    size_t p = pidx(nx, ny, i, j, k);
+                    double ph = cur[p];
+                    double lap = (cur[pidx(nx, ny, i - 1, j, k)] + cur[pidx(nx, ny, i + 1, j, k)]
+                                + cur[pidx(nx, ny, i, j - 1, k)] + cur[pidx(nx, ny, i, j + 1, k)]
+                                + cur[pidx(nx, ny, i, j, k - 1)] + cur[pidx(nx, ny, i, j, k + 1)]
+                                - 6.0 * ph) * idx2;
+                    double s = 4.0 * M_PI * G * rho[((size_t)k * ny + j) * nx + i];
+                    double v = (2.0 * ph - (1.0 - a) * old[p] + c2dt2 * (lap - s)) / (1.0 + a);
+                    nxt[p] = round_storage(v, f32);
+                }
+        /* rotate: old <- cur, cur <- nxt, nxt <- old's storage */
+        double* t = old;
+        old = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    /* hand the results back in the caller's arrays */
+    if (cur != phi_n) {
+        /* the three buffers are {phi_n, phi_nm1, spare}; copy values home */
+        double* tmp_cur = (double*)malloc(np * sizeof(double));
+        double* tmp_old = (double*)malloc(np * sizeof(double));
+        memcpy(tmp_cur, cur, np * sizeof(double));
+        memcpy(tmp_old, old, np * sizeof(double));
+        memcpy(phi_n, tmp_cur, np * sizeof(double));
+        memcpy(phi_nm1, tmp_old, np * sizeof(double));
+        free(tmp_cur);
+        free(tmp_old);
+    } else if (old != phi_nm1) {
+        memcpy(phi_nm1, old, np * sizeof(double));
+    }
+    free(spare);
+}
+
+/* g = -grad phi, central differences with ghosts at the faces; outputs COMPACT. */
+void orc_gradient(int nx, int ny, int nz, double dx, const double* phi,
+                  double* gx, double* gy, double* gz) {
+    double h = 1.0 / (2.0 * dx);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                size_t o = ((size_t)k * ny + j) * nx + i;
+                gx[o] = -(phi[pidx(nx, ny, i + 1, j, k)] - phi[pidx(nx, ny, i - 1, j, k)]) * h;
+                gy[o] = -(phi[pidx(nx, ny, i, j + 1, k)] - phi[pidx(nx, ny, i, j - 1, k)]) * h;
+                gz[o] = -(phi[pidx(nx, ny, i, j, k + 1)] - phi[pidx(nx, ny, i, j, k - 1)]) * h;
+            }
+}
+
+/* Residual of the discrete Poisson problem L_h phi = s, s = 4 pi G rho.
+ * The linear system for the interior unknowns is A phi = b with the ghost
+ * values moved to the right-hand side: b = s - (sum of adjacent ghosts)/dx^2.
+ * out[0] = ||L_h phi - s|| / ||b||   (1 at phi = 0)
+ * out[1] = ||L_h phi - s|| / ||s||
+ * out[2] = ||phi||  (interior, 2-norm)
+ * out[3] = 1 if any interior value of phi or rho is not finite, else 0
+ * A zero denominator gives 0 when the numerator is 0 and +inf otherwise. */
+void orc_residual(int nx, int ny, int nz, double dx, const double* phi, const double* rho,
+                  double G, double* out) {
+    double rr = 0.0, bb = 0.0, ss = 0.0, pp = 0.0;
+    int bad = 0;
+    double idx2 = 1.0 / (dx * dx);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                double c = phi[pidx(nx, ny, i, j, k)];
+                double nb = 0.0, gb = 0.0;
+                int ii[6] = {i - 1, i + 1, i, i, i, i};
+                int jj[6] = {j, j, j - 1, j + 1, j, j};
+                int kk[6] = {k, k, k, k, k - 1, k + 1};
+                for (int q = 0; q < 6; ++q) {
+                    double v = phi[pidx(nx, ny, ii[q], jj[q], kk[q])];
+                    nb += v;
+                    int ghost = ii[q] < 0 || ii[q] >= nx || jj[q] < 0 || jj[q] >= ny || kk[q] < 0 || kk[q] >= nz;
+                    if (ghost) gb += v;
+                }
+                double rhov = rho[((size_t)k * ny + j) * nx + i];
+                double s = 4.0 * M_PI * G * rhov;
+                double r = (nb - 6.0 * c) * idx2 - s;
+                double b = s - gb * idx2;
+                rr += r * r;
+                bb += b * b;
+                ss += s * s;
+                pp += c * c;
+                if (!isfinite(c) || !isfinite(rhov)) bad = 1;
+            }
+    double rn = sqrt(rr);
+    out[0] = bb > 0.0 ? rn / sqrt(bb) : (rn == 0.0 ? 0.0 : INFINITY);
+    out[1] = ss > 0.0 ? rn / sqrt(ss) : (rn == 0.0 ? 0.0 : INFINITY);
+    out[2] = sqrt(pp);
+    out[3] = bad ? 1.0 : 0.0;
+}
+
+int orc_abi_version(void) { return 1; }
