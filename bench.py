@@ -1,0 +1,197 @@
+"""Benchmark of the hyperbolic self-gravity hot path on one MI355X.
+
+One step = one hydrodynamical step of the method: multipole moments of rho and
+the Dirichlet ghost shell, `nsub` leapfrog substeps of Eq. (2) with rho frozen,
+and the acceleration g = -grad phi.  Workload: 512^3 cell-centred grid on
+[-1, 1]^3, FP32 storage with FP64 arithmetic, rho a mixture of 16 Gaussian
+blobs (seed 1) rigidly rotating about z at 0.1 c_g, multipole degree 4,
+4 substeps per hydro step, dt = 0.4 dx / c_g.  Every hydro step gets its own
+rotated density, generated into HBM before the timed region.
+
+Prints one JSON line: Gcell-updates/s (cells x substeps / s) with the
+stencil kernel's roofline, measured with HIP events on the solver's stream,
+and the FP64 CPU oracle timed on the host cores over one hydro step of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources that define the stencil kernels (for the counter file)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1602_05700_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hpp", ".hip")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str, launches_cells: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources and workload; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel)
+        if not e or e.get("source_hash") != kernel_source_hash() or e.get("cells") != launches_cells:
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(rho_host, n, nsub, dt):
+    """The FP64 oracle, as it stands, over one hydro step of the same workload."""
+    import numpy as np
+
+    from oracle import core
+    from oracle.core import Grid, Oracle
+
+    g = Grid.cube(n)
+    o = Oracle(g, lmax=4, eta=0.0)
+    r = np.ascontiguousarray(rho_host, dtype=np.float64)
+    t0 = time.perf_counter()
+    o.step(r, 1.0, dt, nsub)
+    o.accel()
+    t = time.perf_counter() - t0
+    return {
+        "value": nsub * n ** 3 / t / 1e9,
+        "unit": "Gcell-updates/s",
+        "cores": core.max_threads(),
+        "kind": "oracle",
+        "sample": f"one hydro step ({n}^3, moments+ghosts, {nsub} substeps, gradient) in {t:.2f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--nsub", type=int, default=4)
+    ap.add_argument("--tblock", type=int, default=0, help="substeps per fused launch (0 = library default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
+              "described in the design notes but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import hgs
+
+    dev = torch.device("cuda:0")
+    n, nsub, K, W = args.n, args.nsub, args.steps, args.warmup
+    dx = 2.0 / n
+    c_g = 1.0
+    dt = 0.4 * dx / c_g
+    omega = 0.1 * c_g / 1.0  # speed 0.1 c_g at cylindrical radius 1
+    blobs = workloads.blob_params(1, 16)
+    log(f"[bench] generating {W + K} rotated densities {n}^3 fp32 on the GPU")
+    rhos = [workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * h), dev, torch.float32)
+            for h in range(W + K)]
+    s = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=args.tblock, device=dev)
+    out = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in range(3)]
+    stream = s.stream
+
+    log(f"[bench] warmup {W} hydro steps, tblock {s.tblock}")
+    for h in range(W):
+        s.step(rhos[h], c_g, dt, nsub)
+        s.accel(out)
+    torch.cuda.synchronize()
+
+    s.timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for h in range(K):
+        s.step(rhos[W + h], c_g, dt, nsub)
+        s.accel(out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    st = s.timing_read("stencil")
+    mp = s.timing_read("multipole")
+    gr = s.timing_read("gradient")
+    s.timing(False)
+    log(f"[bench] {K} hydro steps: events {ms:.3f} ms, wall {wall * 1e3:.3f} ms")
+    for name, d in (("stencil", st), ("multipole", mp), ("gradient", gr)):
+        if d["launches"]:
+            log(f"[bench]   {name}: {d['launches']} launches, {d['ms'] / d['launches'] * 1e3:.1f} us avg, "
+                f"{d['bytes'] / d['ms'] / 1e6:.0f} GB/s algorithmic")
+
+    updates = K * nsub * n ** 3
+    value = updates / (ms / 1e3) / 1e9
+    per_launch_bytes = st["bytes"] / st["launches"]
+    avg_s = st["ms"] / st["launches"] / 1e3
+    achieved = per_launch_bytes / avg_s / 1e9
+    kname = "leapfrog_stream" if s.tblock == 1 else f"leapfrog_tblock{s.tblock}"
+    traffic = counter_traffic(kname, n ** 3)
+    line = {
+        "metric": "Gcell-updates/s + %HBM roofline; steps to 1e-4 residual, plain vs learned",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-storage/f64-math",
+        "data": "synthetic",
+        "config": {
+            "workload": f"hyperbolic gravity, {n}^3 grid, 16 rotating Gaussian blobs, FP32 storage, lmax 4, "
+                        f"{nsub} substeps per hydro step, moments+ghosts+substeps+gradient",
+            "grid": n, "nsub": nsub, "tblock": s.tblock, "lmax": 4, "blobs": 16,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": kname,
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": per_launch_bytes,
+            "avg_launch_us": round(avg_s * 1e6, 2),
+        },
+        "kernels_us_per_step": {
+            "stencil": round(st["ms"] / K * 1e3, 1),
+            "multipole": round(mp["ms"] / K * 1e3, 1),
+            "gradient": round(gr["ms"] / K * 1e3, 1),
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle, one hydro step)")
+        line["cpu_baseline"] = cpu_baseline(rhos[W].cpu().numpy(), n, nsub, dt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * hgs.h -- C ABI of the MI355X (gfx950) hyperbolic self-gravity library.
+ *
+ * The method (Hirai, Nagakura, Okawa & Fujisawa, arXiv:1602.05700): instead of
+ * solving the Poisson equation  Laplacian(phi) = 4 pi G rho  (Eq. 1), the
+ * potential is advanced in time by the inhomogeneous wave equation
+ *     (-c_g^-2 d^2/dt^2 + Laplacian) phi = 4 pi G rho                (Eq. 2)
+ * by explicit time stepping on the hydrodynamic grid.  Per hydrodynamical step
+ * the density is frozen and the wave equation is sub-cycled with a smaller step
+ * (Sec. 2, separate timelines for gravity and hydrodynamics); the outer
+ * boundary is either a Dirichlet condition from a multipole expansion of rho
+ * (Sec. 2 and Sec. 4, Table I model aD05) or a caller-supplied one; the
+ * gravitational acceleration is g = -grad phi.
+ *
+ * Discretisation (the paper only says "simple discretization", Sec. 2):
+ *   cell-centred uniform grid of nx*ny*nz cubic cells of size dx; cell (i,j,k)
+ *   centre = (x0 + (i+1/2) dx, y0 + (j+1/2) dx, z0 + (k+1/2) dx);
+ *   7-point Laplacian L_h with one layer of ghost cells outside each face;
+ *   3-level leapfrog in time with an optional damping term eta (eta = 0 is
+ *   Eq. 2 exactly; eta > 0 adds eta dphi/dt, which leaves the steady state --
+ *   the discrete Poisson solution -- unchanged and lets a zero start relax):
+ *     phi^{n+1} = [2 phi^n - (1 - a) phi^{n-1} + c^2 dt^2 (L_h phi^n - 4 pi G rho)] / (1 + a),
+ *     a = eta dt / 2.
+ *   Arithmetic is FP64 for every storage dtype; only stored fields are rounded.
+ *
+ * Conventions for every call below.
+ *   - 3D field buffers passed by the caller (rho, phi, phidot, gx, gy, gz, the
+ *     raw state) are DEVICE pointers to contiguous arrays of shape (nz, ny, nx),
+ *     x fastest, element type = cfg.storage.  The caller owns them.
+ *   - Ghost-face buffers hold the six faces back to back in the order
+ *     x-, x+, y-, y+, z-, z+; x faces are (nz, ny) arrays, y faces (nz, nx),
+ *     z faces (ny, nx); ghost centres lie dx/2 outside the face.
+ *     Element type = cfg.storage, device memory.
+ *   - All work is enqueued on cfg.stream (a hipStream_t, NULL = the null
+ *     stream) and is asynchronous, except the calls marked "synchronises".
+ *     Input buffers must stay valid until the stream has passed the call.
+ *   - Every call validates its arguments on the host before enqueueing anything;
+ *     on any non-OK status no state has changed.  No call prints, aborts or
+ *     throws.  hgs_last_error() gives a readable reason for the last failure.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef HGS_H
+#define HGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hgs_ctx hgs_ctx; /* opaque; host memory owned by the library */
+
+typedef enum {
+    HGS_OK = 0,
+    HGS_ERR_ARG = 1,       /* invalid argument (null pointer, bad size, dt <= 0, ...) */
+    HGS_ERR_CFL = 2,       /* c_g dt / dx above 1/sqrt(3), the 3D leapfrog stability limit */
+    HGS_ERR_WORKSPACE = 3, /* workspace missing, too small or misaligned */
+    HGS_ERR_DEVICE = 4,    /* a HIP call failed */
+    HGS_ERR_NONFINITE = 5, /* a synchronising call found NaN/Inf in phi or rho */
+    HGS_ERR_STATE = 6      /* call not valid in the context's current state */
+} hgs_status;
+
+typedef enum { HGS_F64 = 0, HGS_F32 = 1 } hgs_dtype;
+
+typedef enum {
+    HGS_BC_MULTIPOLE = 0, /* Dirichlet ghosts from multipole moments of rho (Sec. 2, Sec. 4) */
+    HGS_BC_USER = 1       /* Dirichlet ghosts set by hgs_set_boundary and kept */
+} hgs_bc;
+
+/* Largest temporal-blocking depth (substeps fused per launch). */
+#define HGS_TMAX 8
+/* Largest multipole degree. */
+#define HGS_LMAX 4
+
+typedef struct {
+    int32_t nx, ny, nz; /* interior cells, each 1..8192 */
+    double x0, y0, z0;  /* lower corner of the interior */
+    double dx;          /* cubic cell size, > 0 */
+    double G;           /* gravitational constant, finite */
+    double origin[3];   /* multipole expansion centre; strictly inside the grid when bc = MULTIPOLE */
+    int32_t lmax;       /* multipole degree 0..HGS_LMAX; 0 gives phi_b = -G M / r */
+    int32_t bc;         /* hgs_bc */
+    int32_t storage;    /* hgs_dtype of every stored field and I/O buffer */
+    int32_t tblock;     /* substeps fused per stencil launch: 1..HGS_TMAX, 0 = library default */
+    double eta;         /* damping rate >= 0; 0 = the paper's Eq. (2) */
+    void* stream;       /* hipStream_t for all work, NULL = null stream */
+} hgs_config;
+
+/* Fill *cfg for an n^3 grid on [lo, hi]^3 with G = 1, origin 0, lmax 4,
+ * multipole boundary, FP32 storage, eta 0, default blocking, null stream. */
+hgs_status hgs_config_cube(hgs_config* cfg, int32_t n, double lo, double hi);
+
+/* Device workspace the context needs, in bytes (the library never allocates
+ * device memory; the caller provides it to hgs_init). */
+hgs_status hgs_workspace_bytes(const hgs_config* cfg, size_t* bytes);
+
+/* Create a context over a caller-owned device workspace of at least
+ * hgs_workspace_bytes(cfg) bytes, 256-byte aligned, that outlives the context.
+ * The state starts at phi = phi_prev = 0 with zero ghosts.  Enqueues fill
+ * kernels on cfg->stream. */
+hgs_status hgs_init(const hgs_config* cfg, void* workspace, size_t bytes, hgs_ctx** out);
+
+/* One hydrodynamical step (Sec. 2): with rho frozen,
+ *   1. (bc = MULTIPOLE) moments Q_lm of rho and the Dirichlet ghosts
+ *      phi_b(x) = -G sum_{l<=lmax} sum_m 4 pi/(2l+1) Q_lm Y_lm(x^) / |x|^{l+1},
+ *      Q_lm = sum_cells rho dx^3 |x|^l conj(Y_lm(x^)), positions relative to
+ *      cfg.origin;
+ *   2. nsub leapfrog substeps of size dt with propagation speed c_g.
+ * If dt differs from the previous step's, phi_prev is first rescaled so that
+ * (phi - phi_prev)/dt is kept.  Errors: HGS_ERR_ARG (null rho, nsub < 1,
+ * dt or c_g not positive and finite), HGS_ERR_CFL (c_g dt / dx > 1/sqrt(3)). */
+hgs_status hgs_step(hgs_ctx* ctx, const void* rho, double c_g, double dt, int32_t nsub);
+
+/* The host-side validation hgs_step applies, without a context or a GPU:
+ * HGS_ERR_ARG for a bad cfg, NULL rho, nsub < 1, dt or c_g not positive and
+ * finite; HGS_ERR_CFL when c_g dt / dx > 1/sqrt(3); else HGS_OK. */
+hgs_status hgs_validate_step(const hgs_config* cfg, const void* rho, double c_g, double dt, int32_t nsub);
+
+/* Copy the current potential out; phidot (nullable) receives the backward
+ * difference (phi^n - phi^{n-1}) / dt of the last step (zero before any step). */
+hgs_status hgs_potential(hgs_ctx* ctx, void* phi, void* phidot);
+
+/* g = -grad phi of the current potential by second-order central
+ * differences, ghosts at the faces; three separate (nz,ny,nx) arrays. */
+hgs_status hgs_accel(hgs_ctx* ctx, void* gx, void* gy, void* gz);
+
+/* Set the state from a potential and its time derivative: phi^n = phi,
+ * phi^{n-1} = phi - dt * phidot (phidot NULL means 0).  dt > 0 becomes the
+ * "previous step" for the dt-rescaling rule of hgs_step. */
+hgs_status hgs_set_state(hgs_ctx* ctx, const void* phi, const void* phidot, double dt);
+
+/* bc = USER only (else HGS_ERR_STATE): set the ghost faces (device, storage
+ * dtype, face layout above).  They stay until the next call. */
+hgs_status hgs_set_boundary(hgs_ctx* ctx, const void* ghosts);
+
+/* Copy the current ghost faces into a device buffer (face layout above). */
+hgs_status hgs_get_boundary(hgs_ctx* ctx, void* ghosts);
+
+/* Synchronises.  The moments of the last hgs_step (bc = MULTIPOLE) as
+ * 2*(lmax+1)^2 doubles on the host: (Re, Im) of Q_lm for l = 0..lmax,
+ * m = -l..l, index l*l + l + m, with orthonormal complex Y_lm including the
+ * Condon-Shortley phase.  HGS_ERR_STATE before the first step. */
+hgs_status hgs_moments(hgs_ctx* ctx, double* q_host);
+
+/* Synchronises.  Residual of the steady state L_h phi = 4 pi G rho (Eq. 1)
+ * for the current phi and the given rho (device, (nz,ny,nx)), on the host:
+ *   out[0] = R_b = ||L_h phi - s|| / ||b||, b = s - (adjacent ghosts)/dx^2
+ *            (the textbook relative residual of the interior linear system;
+ *            1 at phi = 0),
+ *   out[1] = R_f = ||L_h phi - s|| / ||s||,  s = 4 pi G rho,
+ *   out[2] = ||phi|| over the interior,
+ *   out[3] = 1 if phi or rho holds a NaN/Inf (status HGS_ERR_NONFINITE), else 0.
+ * 2-norms over interior cells, FP64.  A zero denominator gives 0 for a zero
+ * numerator and +inf otherwise. */
+hgs_status hgs_residual(hgs_ctx* ctx, const void* rho, double out[4]);
+
+/* Bitwise copy of the raw two-level state (phi^n, phi^{n-1} interiors, device
+ * (nz,ny,nx) buffers) and the previous step size, for checkpoint/resume. */
+hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev);
+hgs_status hgs_load_raw(hgs_ctx* ctx, const void* phi_n, const void* phi_nm1, double dt_prev);
+
+/* Substeps fused per stencil launch for later steps (1..HGS_TMAX, 0 = default). */
+hgs_status hgs_set_tblock(hgs_ctx* ctx, int32_t tblock);
+int32_t hgs_get_tblock(const hgs_ctx* ctx);
+
+/* Per-launch timing with HIP events recorded on the context's stream around
+ * each kernel launch of the given kind, for roofline measurements:
+ *   HGS_KERNEL_STENCIL  the substep launches of hgs_step (streaming or fused),
+ *   HGS_KERNEL_MULTIPOLE the moment and ghost-shell launches of hgs_step,
+ *   HGS_KERNEL_GRADIENT the launches of hgs_accel.
+ * hgs_timing_enable(ctx, 1) clears earlier records and starts recording;
+ * 0 stops.  hgs_timing_read synchronises and returns, for one kind,
+ *   out[0] launches, out[1] summed launch time in ms, out[2] algorithmic HBM
+ *   bytes of those launches (each array element read or written once:
+ *   streaming substep 4 elements per cell, fused launch of T substeps 5,
+ *   moments 1, gradient 4), out[3] cell updates (cells x substeps). */
+typedef enum { HGS_KERNEL_STENCIL = 0, HGS_KERNEL_MULTIPOLE = 1, HGS_KERNEL_GRADIENT = 2 } hgs_kernel_kind;
+hgs_status hgs_timing_enable(hgs_ctx* ctx, int32_t enable);
+hgs_status hgs_timing_read(hgs_ctx* ctx, int32_t kind, double out[4]);
+
+/* Release the host context (the workspace stays the caller's).  NULL is a no-op. */
+hgs_status hgs_destroy(hgs_ctx* ctx);
+
+const char* hgs_status_str(hgs_status s);
+/* Reason for the last non-OK status of this context ("" if none; for a NULL
+ * context, the last failure of hgs_init/hgs_workspace_bytes on this thread). */
+const char* hgs_last_error(const hgs_ctx* ctx);
+
+/* ABI version, bumped on incompatible changes. */
+int32_t hgs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGS_H */

@@ -46,11 +46,18 @@ def lib():
             L.orc_substeps.argtypes = [i, i, i, d, _dp, _dp, _dp, d, d, d, d, i, i]
             L.orc_gradient.argtypes = [i, i, i, d, _dp, _dp, _dp, _dp]
             L.orc_residual.argtypes = [i, i, i, d, _dp, _dp, d, _dp]
+            L.orc_max_threads.restype = ctypes.c_int
+            L.orc_max_threads.argtypes = []
             for f in ("orc_moments", "orc_boundary", "orc_laplacian", "orc_substeps",
                       "orc_gradient", "orc_residual"):
                 getattr(L, f).restype = None
             _lib = L
     return _lib
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_max_threads())
 
 
 def _p(a: np.ndarray):

@@ -30,6 +30,7 @@
  * Parity status of every function is listed in oracle/__init__.py.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -359,3 +360,5 @@ void orc_residual(int nx, int ny, int nz, double dx, const double* phi, const do
 }
 
 int orc_abi_version(void) { return 1; }
+
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -1,0 +1,93 @@
+// Shared device-side definitions of the hyperbolic self-gravity library.
+//
+// Padded field layout in HBM (one per state buffer):
+//   x: interior cell i at element xoff + i of a row; xoff is 128 bytes worth of
+//      elements so every interior row starts on a 128-byte line; the row pitch
+//      is a multiple of 128 bytes with at least HALO spare elements on each side;
+//   y: HALO rows below and above the interior;  z: HALO planes below and above.
+// Ghost cells (the Dirichlet boundary) are the layer adjacent to each face.
+// Everything else outside the interior is padding that no update reads; it
+// lets an extended tile of a temporally blocked launch be loaded without
+// bounds checks.  Padding is filled with NaN at init so that an erroneous
+// read poisons the result instead of passing silently.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hgs.h"
+
+namespace hgs {
+
+constexpr int HALO = HGS_TMAX;  // spare rows/planes around the interior
+constexpr int NQ = (HGS_LMAX + 1) * (HGS_LMAX + 1);  // 25 multipole coefficients
+
+struct Layout {
+    int nx, ny, nz;
+    int xoff;       // element index of interior x = 0 within a row
+    int pitch;      // elements per row
+    int rows;       // ny + 2*HALO
+    int64_t plane;  // pitch * rows
+    int64_t total;  // plane * (nz + 2*HALO)
+
+    __host__ __device__ int64_t idx(int i, int j, int k) const {
+        return ((int64_t)(k + HALO) * rows + (j + HALO)) * pitch + (i + xoff);
+    }
+};
+
+inline Layout make_layout(int nx, int ny, int nz, int elem_bytes) {
+    Layout L;
+    L.nx = nx;
+    L.ny = ny;
+    L.nz = nz;
+    const int line = 128 / elem_bytes;
+    L.xoff = line;  // >= HALO for 4- and 8-byte elements
+    int need = L.xoff + nx + HALO;
+    L.pitch = (need + line - 1) / line * line;
+    L.rows = ny + 2 * HALO;
+    L.plane = (int64_t)L.pitch * L.rows;
+    L.total = L.plane * (nz + 2 * HALO);
+    return L;
+}
+
+// Coefficients of one leapfrog substep, all FP64:
+//   phi^{n+1} = c0 phi + c1 (sum of the six neighbours) + cm phi^{n-1} + cs rho
+// with kk = c^2 dt^2 / dx^2, a = eta dt / 2:
+//   c0 = (2 - 6 kk) / (1 + a), c1 = kk / (1 + a), cm = -(1 - a) / (1 + a),
+//   cs = -c^2 dt^2 4 pi G / (1 + a).
+struct StepCoef {
+    double c0, c1, cm, cs;
+};
+
+// The one place the update is written.  The summation order and the explicit
+// fused multiply-adds are fixed so that every kernel variant (streaming,
+// temporally blocked, batched) produces bit-identical results.
+__device__ __forceinline__ double leapfrog_update(const StepCoef& c, double p, double xm, double xp, double ym,
+                                                  double yp, double zm, double zp, double old, double rho) {
+    double nb = ((xm + xp) + (ym + yp)) + (zm + zp);
+    return fma(c.cs, rho, fma(c.cm, old, fma(c.c1, nb, c.c0 * p)));
+}
+
+template <typename S>
+__device__ __forceinline__ double ld(const S* p) {
+    return (double)(*p);
+}
+
+// Workgroups of one launch are handed to the 8 XCDs round-robin.  Renumber
+// them so that XCD x runs a contiguous range of tiles: neighbouring tiles then
+// share that XCD's L2 for their halos.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+    const int nx = 8;
+    int q = nblocks / nx, r = nblocks % nx;
+    int xcd = bid % nx, local = bid / nx;
+    return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace hgs

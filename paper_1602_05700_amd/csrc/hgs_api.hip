@@ -1,0 +1,689 @@
+// Host side of the C ABI declared in include/hgs.h.
+//
+// The library never allocates device memory: hgs_init carves the caller's
+// workspace into four padded state buffers (two levels in use, two more for
+// the out-of-place temporally blocked launches), the moment partials and the
+// reduction scratch.  Every entry point validates on the host first and only
+// then enqueues work on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hgs.h"
+#include "common.hpp"
+#include "k_multipole.hpp"
+#include "k_state.hpp"
+#include "k_stencil.hpp"
+#include "k_tblock.hpp"
+
+using namespace hgs;
+
+struct hgs_ctx {
+    hgs_config cfg;
+    Layout L;
+    hipStream_t stream;
+    int esize;
+    void* buf[4];
+    int cur, old;  // buffers holding phi^n and phi^{n-1}
+    double* mom_partial;
+    double* mom;
+    int mom_blocks, mom_zc, mom_tx, mom_ty;
+    double* red_partial;
+    double* red_out;
+    int red_blocks;
+    double dt_prev;
+    bool have_moments;
+    int tblock;
+    std::string err;
+    // launch timing (hgs_timing_*)
+    bool timing;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+        double bytes, updates;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr int kMaxN = 8192;
+constexpr size_t kAlign = 256;
+constexpr int kRedBlocks = 1024;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+hgs_status fail(hgs_ctx* c, hgs_status s, const std::string& msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_err = msg;
+    return s;
+}
+
+struct Plan {
+    size_t buf_bytes;  // one padded state buffer
+    size_t mom_partial_off, mom_off, red_partial_off, red_out_off, total;
+    int mom_blocks, mom_zc, mom_tx, mom_ty;
+};
+
+hgs_status check_config(const hgs_config* cfg, std::string& why) {
+    if (!cfg) {
+        why = "cfg is NULL";
+        return HGS_ERR_ARG;
+    }
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1 || cfg->nx > kMaxN || cfg->ny > kMaxN || cfg->nz > kMaxN) {
+        why = "grid sizes must be in 1..8192";
+        return HGS_ERR_ARG;
+    }
+    if (!(cfg->dx > 0.0) || !std::isfinite(cfg->dx)) {
+        why = "dx must be positive and finite";
+        return HGS_ERR_ARG;
+    }
+    if (!std::isfinite(cfg->x0) || !std::isfinite(cfg->y0) || !std::isfinite(cfg->z0) || !std::isfinite(cfg->G) ||
+        !std::isfinite(cfg->origin[0]) || !std::isfinite(cfg->origin[1]) || !std::isfinite(cfg->origin[2])) {
+        why = "x0, y0, z0, G and origin must be finite";
+        return HGS_ERR_ARG;
+    }
+    if (cfg->lmax < 0 || cfg->lmax > HGS_LMAX) {
+        why = "lmax must be in 0..4";
+        return HGS_ERR_ARG;
+    }
+    if (cfg->bc != HGS_BC_MULTIPOLE && cfg->bc != HGS_BC_USER) {
+        why = "bc must be HGS_BC_MULTIPOLE or HGS_BC_USER";
+        return HGS_ERR_ARG;
+    }
+    if (cfg->storage != HGS_F64 && cfg->storage != HGS_F32) {
+        why = "storage must be HGS_F64 or HGS_F32";
+        return HGS_ERR_ARG;
+    }
+    if (cfg->tblock < 0 || cfg->tblock > HGS_TMAX) {
+        why = "tblock must be in 0..8";
+        return HGS_ERR_ARG;
+    }
+    if (!(cfg->eta >= 0.0) || !std::isfinite(cfg->eta)) {
+        why = "eta must be >= 0 and finite";
+        return HGS_ERR_ARG;
+    }
+    if (cfg->bc == HGS_BC_MULTIPOLE) {
+        // the exterior expansion is evaluated at the ghost centres; with the
+        // centre strictly inside the grid they all lie at r >= dx/2 > 0
+        const double lo[3] = {cfg->x0, cfg->y0, cfg->z0};
+        const int n[3] = {cfg->nx, cfg->ny, cfg->nz};
+        for (int d = 0; d < 3; ++d)
+            if (!(cfg->origin[d] > lo[d] && cfg->origin[d] < lo[d] + n[d] * cfg->dx)) {
+                why = "the multipole expansion centre must lie strictly inside the grid";
+                return HGS_ERR_ARG;
+            }
+    }
+    int es = cfg->storage == HGS_F64 ? 8 : 4;
+    Layout L = make_layout(cfg->nx, cfg->ny, cfg->nz, es);
+    if (L.total >= ((int64_t)1 << 31)) {
+        why = "grid too large for one buffer (padded elements must stay below 2^31)";
+        return HGS_ERR_ARG;
+    }
+    return HGS_OK;
+}
+
+Plan make_plan(const hgs_config* cfg) {
+    Plan p;
+    int es = cfg->storage == HGS_F64 ? 8 : 4;
+    Layout L = make_layout(cfg->nx, cfg->ny, cfg->nz, es);
+    p.buf_bytes = align_up((size_t)L.total * es, kAlign);
+    // moments: 64 x 4 column tiles; split z so that there are >= 2048 workgroups when possible
+    p.mom_tx = (cfg->nx + 63) / 64;
+    p.mom_ty = (cfg->ny + 3) / 4;
+    int cols = p.mom_tx * p.mom_ty;
+    int zsplit = std::max(1, std::min(cfg->nz, (2048 + cols - 1) / cols));
+    p.mom_zc = (cfg->nz + zsplit - 1) / zsplit;
+    p.mom_blocks = cols * ((cfg->nz + p.mom_zc - 1) / p.mom_zc);
+    size_t off = 4 * p.buf_bytes;
+    p.mom_partial_off = off;
+    off = align_up(off + (size_t)p.mom_blocks * NQ * sizeof(double), kAlign);
+    p.mom_off = off;
+    off = align_up(off + NQ * sizeof(double), kAlign);
+    p.red_partial_off = off;
+    off = align_up(off + (size_t)kRedBlocks * NRED * sizeof(double), kAlign);
+    p.red_out_off = off;
+    off = align_up(off + NRED * sizeof(double), kAlign);
+    p.total = off;
+    return p;
+}
+
+template <typename S>
+S* B(hgs_ctx* c, int k) {
+    return static_cast<S*>(c->buf[k]);
+}
+
+hgs_status launch_check(hgs_ctx* c, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, HGS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return HGS_OK;
+}
+
+int grid_for(int64_t n, int block = 256, int cap = 65536) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+MomGeom geom(const hgs_ctx* c) {
+    MomGeom g;
+    g.nx = c->cfg.nx;
+    g.ny = c->cfg.ny;
+    g.nz = c->cfg.nz;
+    g.x0 = c->cfg.x0;
+    g.y0 = c->cfg.y0;
+    g.z0 = c->cfg.z0;
+    g.dx = c->cfg.dx;
+    g.ox = c->cfg.origin[0];
+    g.oy = c->cfg.origin[1];
+    g.oz = c->cfg.origin[2];
+    return g;
+}
+
+StepCoef step_coef(const hgs_ctx* c, double cg, double dt) {
+    const double c2dt2 = cg * cg * dt * dt;
+    const double kk = c2dt2 / (c->cfg.dx * c->cfg.dx);
+    const double a = 0.5 * c->cfg.eta * dt;
+    const double inv = 1.0 / (1.0 + a);
+    StepCoef s;
+    s.c0 = (2.0 - 6.0 * kk) * inv;
+    s.c1 = kk * inv;
+    s.cm = -(1.0 - a) * inv;
+    s.cs = -c2dt2 * 4.0 * M_PI * c->cfg.G * inv;
+    return s;
+}
+
+// ---- launch timing ----------------------------------------------------------
+
+hipEvent_t pool_event(hgs_ctx* c) {
+    if (c->pool_used == c->pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->pool.push_back(e);
+    }
+    return c->pool[c->pool_used++];
+}
+
+// Brackets one launch: call begin() before it and end() after it.
+struct Timed {
+    hgs_ctx* c;
+    hipEvent_t a = nullptr;
+    int kind;
+    Timed(hgs_ctx* ctx, int k) : c(ctx), kind(k) {
+        if (c->timing) {
+            a = pool_event(c);
+            if (a && hipEventRecord(a, c->stream) != hipSuccess) a = nullptr;
+        }
+    }
+    void end(double bytes, double updates) {
+        if (!a) return;
+        hipEvent_t b = pool_event(c);
+        if (!b) return;
+        if (hipEventRecord(b, c->stream) != hipSuccess) return;
+        c->recs.push_back({kind, a, b, bytes, updates});
+    }
+};
+
+// ---- launches, templated on the storage type ---------------------------------
+
+constexpr int SBX = 64, SBY = 4;  // streaming tile
+
+template <typename S>
+void stream_dims(const Layout& L, int& zc, int& tiles_x, int& tiles_y, int& nblocks) {
+    tiles_x = (L.nx + SBX - 1) / SBX;
+    tiles_y = (L.ny + SBY - 1) / SBY;
+    int cols = tiles_x * tiles_y;
+    // enough workgroups to fill 256 CUs several times over, z chunks >= 16 planes
+    int zsplit = std::max(1, std::min((L.nz + 15) / 16, (4096 + cols - 1) / cols));
+    zc = (L.nz + zsplit - 1) / zsplit;
+    nblocks = cols * ((L.nz + zc - 1) / zc);
+}
+
+template <typename S>
+void run_moments_and_ghosts(hgs_ctx* c, const void* rho) {
+    const MomGeom g = geom(c);
+    Timed tm(c, HGS_KERNEL_MULTIPOLE);
+    dim3 blk(64, 4);
+    hipLaunchKernelGGL(k_moments_partial<S>, dim3(c->mom_blocks), blk, 0, c->stream, static_cast<const S*>(rho), g,
+                       c->mom_zc, c->mom_tx, c->mom_ty, c->mom_partial);
+    hipLaunchKernelGGL(k_moments_final, dim3(NQ), dim3(256), 0, c->stream, c->mom_partial, c->mom_blocks,
+                       c->cfg.dx * c->cfg.dx * c->cfg.dx, c->mom);
+    const int64_t nf = 2 * ((int64_t)c->L.nz * c->L.ny + (int64_t)c->L.nz * c->L.nx + (int64_t)c->L.ny * c->L.nx);
+    hipLaunchKernelGGL(k_ghosts<S>, dim3(grid_for(nf)), dim3(256), 0, c->stream, c->L, g, c->cfg.lmax, c->cfg.G,
+                       c->mom, B<S>(c, 0), B<S>(c, 1), B<S>(c, 2), B<S>(c, 3));
+    tm.end((double)sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz + 4.0 * sizeof(S) * (double)nf, 0.0);
+}
+
+template <typename S>
+void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub) {
+    const S* r = static_cast<const S*>(rho);
+    int T = c->tblock;
+    while (nsub > 0) {
+        if (kTBlockAvailable && T > 1 && nsub >= T) {
+            // out of place: (cur, old) -> (the other two buffers)
+            int o0 = -1, o1 = -1;
+            for (int k = 0; k < 4; ++k)
+                if (k != c->cur && k != c->old) {
+                    if (o0 < 0)
+                        o0 = k;
+                    else
+                        o1 = k;
+                }
+            Timed tm(c, HGS_KERNEL_STENCIL);
+            launch_tblock<S>(B<S>(c, c->cur), B<S>(c, c->old), r, B<S>(c, o0), B<S>(c, o1), c->L, sc, T, c->stream);
+            const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
+            tm.end(5.0 * sizeof(S) * cells, cells * T);
+            c->cur = o0;
+            c->old = o1;
+            nsub -= T;
+        } else {
+            int zc, tx, ty, nb;
+            stream_dims<S>(c->L, zc, tx, ty, nb);
+            Timed tm(c, HGS_KERNEL_STENCIL);
+            hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream,
+                               B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty);
+            const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
+            tm.end(4.0 * sizeof(S) * cells, cells);
+            std::swap(c->cur, c->old);
+            nsub -= 1;
+        }
+    }
+}
+
+template <typename S>
+void run_accel(hgs_ctx* c, void* gx, void* gy, void* gz) {
+    int zc, tx, ty, nb;
+    stream_dims<S>(c->L, zc, tx, ty, nb);
+    Timed tm(c, HGS_KERNEL_GRADIENT);
+    hipLaunchKernelGGL((k_gradient<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream, B<S>(c, c->cur), c->L,
+                       0.5 / c->cfg.dx, zc, tx, ty, static_cast<S*>(gx), static_cast<S*>(gy), static_cast<S*>(gz));
+    tm.end(4.0 * sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz, 0.0);
+}
+
+template <typename S>
+void run_init(hgs_ctx* c) {
+    for (int k = 0; k < 4; ++k)
+        hipLaunchKernelGGL(k_init_buffer<S>, dim3(grid_for(c->L.total)), dim3(256), 0, c->stream, B<S>(c, k), c->L);
+}
+
+int64_t ncell(const hgs_ctx* c) { return (int64_t)c->cfg.nx * c->cfg.ny * c->cfg.nz; }
+int64_t nface(const hgs_ctx* c) {
+    return 2 * ((int64_t)c->L.nz * c->L.ny + (int64_t)c->L.nz * c->L.nx + (int64_t)c->L.ny * c->L.nx);
+}
+
+#define DISPATCH(c, fn, ...)                   \
+    do {                                       \
+        if ((c)->cfg.storage == HGS_F64)       \
+            fn<double>(__VA_ARGS__);           \
+        else                                   \
+            fn<float>(__VA_ARGS__);            \
+    } while (0)
+
+template <typename S>
+void run_potential(hgs_ctx* c, void* phi, void* phidot) {
+    double inv = c->dt_prev > 0.0 ? 1.0 / c->dt_prev : 0.0;
+    hipLaunchKernelGGL(k_potential<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, B<S>(c, c->cur),
+                       B<S>(c, c->old), inv, c->L, static_cast<S*>(phi), static_cast<S*>(phidot));
+}
+
+template <typename S>
+void run_set_state(hgs_ctx* c, const void* phi, const void* phidot, double dt) {
+    hipLaunchKernelGGL(k_set_state<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, B<S>(c, c->cur),
+                       B<S>(c, c->old), static_cast<const S*>(phi), static_cast<const S*>(phidot), dt, c->L);
+}
+
+template <typename S>
+void run_rescale(hgs_ctx* c, double ratio) {
+    hipLaunchKernelGGL(k_rescale<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, B<S>(c, c->cur),
+                       B<S>(c, c->old), ratio, c->L);
+}
+
+template <typename S>
+void run_faces_in(hgs_ctx* c, const void* src) {
+    hipLaunchKernelGGL(k_faces_in<S>, dim3(grid_for(nface(c))), dim3(256), 0, c->stream, static_cast<const S*>(src),
+                       c->L, B<S>(c, 0), B<S>(c, 1), B<S>(c, 2), B<S>(c, 3));
+}
+
+template <typename S>
+void run_faces_out(hgs_ctx* c, void* dst) {
+    hipLaunchKernelGGL(k_faces_out<S>, dim3(grid_for(nface(c))), dim3(256), 0, c->stream, B<S>(c, c->cur), c->L,
+                       static_cast<S*>(dst));
+}
+
+template <typename S>
+void run_residual(hgs_ctx* c, const void* rho) {
+    const double idx2 = 1.0 / (c->cfg.dx * c->cfg.dx);
+    int nb = grid_for(ncell(c), 256, kRedBlocks);
+    hipLaunchKernelGGL(k_residual_partial<S>, dim3(nb), dim3(256), 0, c->stream, B<S>(c, c->cur),
+                       static_cast<const S*>(rho), c->L, idx2, 4.0 * M_PI * c->cfg.G, c->red_partial);
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, c->stream, c->red_partial, nb, c->red_out);
+}
+
+template <typename S>
+void run_raw_out(hgs_ctx* c, void* a, void* b) {
+    hipLaunchKernelGGL(k_interior_out<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, B<S>(c, c->cur), c->L,
+                       static_cast<S*>(a));
+    hipLaunchKernelGGL(k_interior_out<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, B<S>(c, c->old), c->L,
+                       static_cast<S*>(b));
+}
+
+template <typename S>
+void run_raw_in(hgs_ctx* c, const void* a, const void* b) {
+    hipLaunchKernelGGL(k_interior_in<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream,
+                       static_cast<const S*>(a), c->L, B<S>(c, c->cur));
+    hipLaunchKernelGGL(k_interior_in<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream,
+                       static_cast<const S*>(b), c->L, B<S>(c, c->old));
+}
+
+int default_tblock(const hgs_config* cfg) { return cfg->tblock > 0 ? cfg->tblock : 1; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t hgs_abi_version(void) { return 1; }
+
+const char* hgs_status_str(hgs_status s) {
+    switch (s) {
+        case HGS_OK: return "HGS_OK";
+        case HGS_ERR_ARG: return "HGS_ERR_ARG";
+        case HGS_ERR_CFL: return "HGS_ERR_CFL";
+        case HGS_ERR_WORKSPACE: return "HGS_ERR_WORKSPACE";
+        case HGS_ERR_DEVICE: return "HGS_ERR_DEVICE";
+        case HGS_ERR_NONFINITE: return "HGS_ERR_NONFINITE";
+        case HGS_ERR_STATE: return "HGS_ERR_STATE";
+    }
+    return "HGS_ERR_UNKNOWN";
+}
+
+const char* hgs_last_error(const hgs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+hgs_status hgs_config_cube(hgs_config* cfg, int32_t n, double lo, double hi) {
+    if (!cfg) return fail(nullptr, HGS_ERR_ARG, "cfg is NULL");
+    if (n < 1 || n > kMaxN || !(hi > lo)) return fail(nullptr, HGS_ERR_ARG, "need 1 <= n <= 8192 and hi > lo");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->nx = cfg->ny = cfg->nz = n;
+    cfg->x0 = cfg->y0 = cfg->z0 = lo;
+    cfg->dx = (hi - lo) / n;
+    cfg->G = 1.0;
+    cfg->lmax = HGS_LMAX;
+    cfg->bc = HGS_BC_MULTIPOLE;
+    cfg->storage = HGS_F32;
+    cfg->tblock = 0;
+    cfg->eta = 0.0;
+    cfg->stream = nullptr;
+    return HGS_OK;
+}
+
+hgs_status hgs_workspace_bytes(const hgs_config* cfg, size_t* bytes) {
+    std::string why;
+    hgs_status s = check_config(cfg, why);
+    if (s != HGS_OK) return fail(nullptr, s, why);
+    if (!bytes) return fail(nullptr, HGS_ERR_ARG, "bytes is NULL");
+    *bytes = make_plan(cfg).total;
+    return HGS_OK;
+}
+
+hgs_status hgs_init(const hgs_config* cfg, void* workspace, size_t bytes, hgs_ctx** out) {
+    std::string why;
+    hgs_status s = check_config(cfg, why);
+    if (s != HGS_OK) return fail(nullptr, s, why);
+    if (!out) return fail(nullptr, HGS_ERR_ARG, "out is NULL");
+    Plan p = make_plan(cfg);
+    if (!workspace) return fail(nullptr, HGS_ERR_WORKSPACE, "workspace is NULL");
+    if (bytes < p.total) return fail(nullptr, HGS_ERR_WORKSPACE, "workspace smaller than hgs_workspace_bytes()");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(nullptr, HGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    hgs_ctx* c = new (std::nothrow) hgs_ctx();
+    if (!c) return fail(nullptr, HGS_ERR_ARG, "out of host memory");
+    c->cfg = *cfg;
+    c->esize = cfg->storage == HGS_F64 ? 8 : 4;
+    c->L = make_layout(cfg->nx, cfg->ny, cfg->nz, c->esize);
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+    char* w = static_cast<char*>(workspace);
+    for (int k = 0; k < 4; ++k) c->buf[k] = w + k * p.buf_bytes;
+    c->cur = 0;
+    c->old = 1;
+    c->mom_partial = reinterpret_cast<double*>(w + p.mom_partial_off);
+    c->mom = reinterpret_cast<double*>(w + p.mom_off);
+    c->mom_blocks = p.mom_blocks;
+    c->mom_zc = p.mom_zc;
+    c->mom_tx = p.mom_tx;
+    c->mom_ty = p.mom_ty;
+    c->red_partial = reinterpret_cast<double*>(w + p.red_partial_off);
+    c->red_out = reinterpret_cast<double*>(w + p.red_out_off);
+    c->red_blocks = kRedBlocks;
+    c->dt_prev = 0.0;
+    c->have_moments = false;
+    c->tblock = default_tblock(cfg);
+    c->timing = false;
+    c->pool_used = 0;
+    (void)hipGetLastError();
+    DISPATCH(c, run_init, c);
+    s = launch_check(c, "hgs_init");
+    if (s != HGS_OK) {
+        g_err = c->err;
+        delete c;
+        return s;
+    }
+    *out = c;
+    return HGS_OK;
+}
+
+hgs_status hgs_destroy(hgs_ctx* ctx) {
+    if (ctx) {
+        if (!ctx->pool.empty()) (void)hipStreamSynchronize(ctx->stream);
+        for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+    return HGS_OK;
+}
+
+hgs_status hgs_timing_enable(hgs_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (enable) {
+        // events in the pool may still be pending on the stream
+        if (!ctx->pool.empty() && hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return fail(ctx, HGS_ERR_DEVICE, "hgs_timing_enable: stream synchronisation failed");
+        ctx->recs.clear();
+        ctx->pool_used = 0;
+    }
+    ctx->timing = enable != 0;
+    return HGS_OK;
+}
+
+hgs_status hgs_timing_read(hgs_ctx* ctx, int32_t kind, double out[4]) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!out || kind < 0 || kind > 2) return fail(ctx, HGS_ERR_ARG, "out must be non-NULL and kind in 0..2");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, HGS_ERR_DEVICE, std::string("hgs_timing_read: ") + hipGetErrorString(e));
+    double n = 0, ms = 0, bytes = 0, upd = 0;
+    for (const auto& r : ctx->recs) {
+        if (r.kind != kind) continue;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return fail(ctx, HGS_ERR_DEVICE, "event timing failed");
+        n += 1;
+        ms += t;
+        bytes += r.bytes;
+        upd += r.updates;
+    }
+    out[0] = n;
+    out[1] = ms;
+    out[2] = bytes;
+    out[3] = upd;
+    return HGS_OK;
+}
+
+hgs_status hgs_set_tblock(hgs_ctx* ctx, int32_t tblock) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (tblock < 0 || tblock > HGS_TMAX) return fail(ctx, HGS_ERR_ARG, "tblock must be in 0..8");
+    ctx->tblock = tblock == 0 ? 1 : tblock;
+    return HGS_OK;
+}
+
+int32_t hgs_get_tblock(const hgs_ctx* ctx) { return ctx ? ctx->tblock : 0; }
+
+static hgs_status validate_step(hgs_ctx* ctx, const hgs_config* cfg, const void* rho, double c_g, double dt,
+                                int32_t nsub) {
+    if (!rho) return fail(ctx, HGS_ERR_ARG, "rho is NULL");
+    if (nsub < 1) return fail(ctx, HGS_ERR_ARG, "nsub must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, HGS_ERR_ARG, "dt must be positive and finite");
+    if (!(c_g > 0.0) || !std::isfinite(c_g)) return fail(ctx, HGS_ERR_ARG, "c_g must be positive and finite");
+    const double courant = c_g * dt / cfg->dx;
+    if (courant > 1.0 / std::sqrt(3.0)) {
+        char m[160];
+        std::snprintf(m, sizeof m, "c_g dt / dx = %.6g exceeds the 3D leapfrog limit 1/sqrt(3)", courant);
+        return fail(ctx, HGS_ERR_CFL, m);
+    }
+    return HGS_OK;
+}
+
+hgs_status hgs_validate_step(const hgs_config* cfg, const void* rho, double c_g, double dt, int32_t nsub) {
+    std::string why;
+    hgs_status s = check_config(cfg, why);
+    if (s != HGS_OK) return fail(nullptr, s, why);
+    return validate_step(nullptr, cfg, rho, c_g, dt, nsub);
+}
+
+hgs_status hgs_step(hgs_ctx* ctx, const void* rho, double c_g, double dt, int32_t nsub) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    hgs_status vs = validate_step(ctx, &ctx->cfg, rho, c_g, dt, nsub);
+    if (vs != HGS_OK) return vs;
+    (void)hipGetLastError();
+    if (ctx->cfg.bc == HGS_BC_MULTIPOLE) {
+        DISPATCH(ctx, run_moments_and_ghosts, ctx, rho);
+        ctx->have_moments = true;
+    }
+    if (ctx->dt_prev > 0.0 && dt != ctx->dt_prev) DISPATCH(ctx, run_rescale, ctx, dt / ctx->dt_prev);
+    DISPATCH(ctx, run_substeps, ctx, rho, step_coef(ctx, c_g, dt), nsub);
+    ctx->dt_prev = dt;
+    return launch_check(ctx, "hgs_step");
+}
+
+hgs_status hgs_potential(hgs_ctx* ctx, void* phi, void* phidot) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!phi) return fail(ctx, HGS_ERR_ARG, "phi is NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_potential, ctx, phi, phidot);
+    return launch_check(ctx, "hgs_potential");
+}
+
+hgs_status hgs_accel(hgs_ctx* ctx, void* gx, void* gy, void* gz) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!gx || !gy || !gz) return fail(ctx, HGS_ERR_ARG, "gx, gy and gz must be non-NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_accel, ctx, gx, gy, gz);
+    return launch_check(ctx, "hgs_accel");
+}
+
+hgs_status hgs_set_state(hgs_ctx* ctx, const void* phi, const void* phidot, double dt) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!phi) return fail(ctx, HGS_ERR_ARG, "phi is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, HGS_ERR_ARG, "dt must be positive and finite");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_set_state, ctx, phi, phidot, dt);
+    ctx->dt_prev = dt;
+    return launch_check(ctx, "hgs_set_state");
+}
+
+hgs_status hgs_set_boundary(hgs_ctx* ctx, const void* ghosts) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (ctx->cfg.bc != HGS_BC_USER) return fail(ctx, HGS_ERR_STATE, "hgs_set_boundary needs bc = HGS_BC_USER");
+    if (!ghosts) return fail(ctx, HGS_ERR_ARG, "ghosts is NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_faces_in, ctx, ghosts);
+    return launch_check(ctx, "hgs_set_boundary");
+}
+
+hgs_status hgs_get_boundary(hgs_ctx* ctx, void* ghosts) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!ghosts) return fail(ctx, HGS_ERR_ARG, "ghosts is NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_faces_out, ctx, ghosts);
+    return launch_check(ctx, "hgs_get_boundary");
+}
+
+hgs_status hgs_moments(hgs_ctx* ctx, double* q_host) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!q_host) return fail(ctx, HGS_ERR_ARG, "q_host is NULL");
+    if (!ctx->have_moments) return fail(ctx, HGS_ERR_STATE, "no moments before the first multipole step");
+    double ab[NQ];
+    hipError_t e = hipMemcpyAsync(ab, ctx->mom, sizeof ab, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, HGS_ERR_DEVICE, std::string("hgs_moments: ") + hipGetErrorString(e));
+    // A_lm + i B_lm = sum m r^l P_l^m e^{i m phi} (no Condon-Shortley phase).  With
+    // Y_lm = N_lm (-1)^m P_l^m e^{i m phi}:  Q_lm = N_lm (-1)^m (A_lm - i B_lm), m >= 0,
+    // and Q_{l,-m} = (-1)^m conj(Q_lm).
+    const int lmax = ctx->cfg.lmax;
+    for (int l = 0; l <= lmax; ++l) {
+        for (int m = 0; m <= l; ++m) {
+            double ratio = 1.0;
+            for (int f = l - m + 1; f <= l + m; ++f) ratio /= (double)f;
+            const double N = std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * ratio);
+            const double sg = (m % 2) ? -1.0 : 1.0;
+            const double A = ab[l * l + l + m];
+            const double Bv = m > 0 ? ab[l * l + l - m] : 0.0;
+            const double re = N * sg * A, im = -N * sg * Bv;
+            q_host[2 * (l * l + l + m)] = re;
+            q_host[2 * (l * l + l + m) + 1] = im;
+            if (m > 0) {
+                q_host[2 * (l * l + l - m)] = sg * re;
+                q_host[2 * (l * l + l - m) + 1] = -sg * im;
+            }
+        }
+    }
+    return HGS_OK;
+}
+
+hgs_status hgs_residual(hgs_ctx* ctx, const void* rho, double out[4]) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!rho || !out) return fail(ctx, HGS_ERR_ARG, "rho and out must be non-NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_residual, ctx, rho);
+    hgs_status s = launch_check(ctx, "hgs_residual");
+    if (s != HGS_OK) return s;
+    double r[NRED];
+    hipError_t e = hipMemcpyAsync(r, ctx->red_out, sizeof r, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, HGS_ERR_DEVICE, std::string("hgs_residual: ") + hipGetErrorString(e));
+    const double rn = std::sqrt(r[0]);
+    out[0] = r[1] > 0.0 ? rn / std::sqrt(r[1]) : (rn == 0.0 ? 0.0 : INFINITY);
+    out[1] = r[2] > 0.0 ? rn / std::sqrt(r[2]) : (rn == 0.0 ? 0.0 : INFINITY);
+    out[2] = std::sqrt(r[3]);
+    out[3] = r[4] > 0.0 ? 1.0 : 0.0;
+    if (out[3] != 0.0) return fail(ctx, HGS_ERR_NONFINITE, "phi or rho holds a non-finite value");
+    return HGS_OK;
+}
+
+hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!phi_n || !phi_nm1 || !dt_prev) return fail(ctx, HGS_ERR_ARG, "phi_n, phi_nm1 and dt_prev must be non-NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_raw_out, ctx, phi_n, phi_nm1);
+    *dt_prev = ctx->dt_prev;
+    return launch_check(ctx, "hgs_save_raw");
+}
+
+hgs_status hgs_load_raw(hgs_ctx* ctx, const void* phi_n, const void* phi_nm1, double dt_prev) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!phi_n || !phi_nm1) return fail(ctx, HGS_ERR_ARG, "phi_n and phi_nm1 must be non-NULL");
+    if (!(dt_prev >= 0.0) || !std::isfinite(dt_prev)) return fail(ctx, HGS_ERR_ARG, "dt_prev must be >= 0");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_raw_in, ctx, phi_n, phi_nm1);
+    ctx->dt_prev = dt_prev;
+    return launch_check(ctx, "hgs_load_raw");
+}
+
+}  // extern "C"

@@ -1,0 +1,235 @@
+// State bookkeeping kernels (fill, set_state, dt rescale, readback, raw copies,
+// ghost faces) and the FP64 residual norms of the steady state L_h phi = 4 pi G rho.
+#pragma once
+
+#include "common.hpp"
+
+namespace hgs {
+
+// Interior cells are addressed through a flat index t in [0, nx*ny*nz):
+// i = t % nx, j = (t / nx) % ny, k = t / (nx*ny), i.e. the caller's compact layout.
+struct Flat {
+    int i, j, k;
+};
+__device__ __forceinline__ Flat unflat(int64_t t, const Layout& L) {
+    Flat f;
+    f.i = (int)(t % L.nx);
+    int64_t r = t / L.nx;
+    f.j = (int)(r % L.ny);
+    f.k = (int)(r / L.ny);
+    return f;
+}
+
+#define HGS_GRID_STRIDE(t, n) \
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (n); t += (int64_t)gridDim.x * blockDim.x)
+
+// Whole padded buffer: NaN everywhere, then 0 on the interior and the six ghost
+// faces (edges and corners of the ghost box and all other padding stay NaN).
+template <typename S>
+__global__ void k_init_buffer(S* b, Layout L) {
+    HGS_GRID_STRIDE(t, L.total) {
+        int64_t kz = t / L.plane;
+        int64_t rem = t % L.plane;
+        int jy = (int)(rem / L.pitch);
+        int ix = (int)(rem % L.pitch);
+        int i = ix - L.xoff, j = jy - HALO, k = (int)kz - HALO;
+        int outside = (i < 0 || i >= L.nx) + (j < 0 || j >= L.ny) + (k < 0 || k >= L.nz);
+        bool in_box = i >= -1 && i <= L.nx && j >= -1 && j <= L.ny && k >= -1 && k <= L.nz;
+        b[t] = (in_box && outside <= 1) ? (S)0 : (S)__builtin_nan("");
+    }
+}
+
+template <typename S>
+__global__ void k_set_state(S* cur, S* old, const S* __restrict__ phi, const S* __restrict__ phidot, double dt,
+                            Layout L) {
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = unflat(t, L);
+        int64_t o = L.idx(f.i, f.j, f.k);
+        double p = (double)phi[t];
+        double pd = phidot ? (double)phidot[t] : 0.0;
+        cur[o] = (S)p;
+        old[o] = (S)(p - dt * pd);
+    }
+}
+
+// phi^{n-1} <- phi^n - ratio (phi^n - phi^{n-1}), ratio = dt_new / dt_old.
+template <typename S>
+__global__ void k_rescale(const S* __restrict__ cur, S* old, double ratio, Layout L) {
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = unflat(t, L);
+        int64_t o = L.idx(f.i, f.j, f.k);
+        double c = (double)cur[o];
+        double d = c - (double)old[o];
+        double u = ratio * d;
+        old[o] = (S)(c - u);
+    }
+}
+
+template <typename S>
+__global__ void k_potential(const S* __restrict__ cur, const S* __restrict__ old, double inv_dt, Layout L,
+                            S* __restrict__ phi, S* __restrict__ phidot) {
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = unflat(t, L);
+        int64_t o = L.idx(f.i, f.j, f.k);
+        double c = (double)cur[o];
+        if (phi) phi[t] = (S)c;
+        if (phidot) phidot[t] = (inv_dt > 0.0) ? (S)((c - (double)old[o]) * inv_dt) : (S)0;
+    }
+}
+
+// Raw interior copy, padded <-> compact, bit-exact.
+template <typename S>
+__global__ void k_interior_out(const S* __restrict__ src, Layout L, S* __restrict__ dst) {
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = unflat(t, L);
+        dst[t] = src[L.idx(f.i, f.j, f.k)];
+    }
+}
+template <typename S>
+__global__ void k_interior_in(const S* __restrict__ src, Layout L, S* __restrict__ dst) {
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = unflat(t, L);
+        dst[L.idx(f.i, f.j, f.k)] = src[t];
+    }
+}
+
+// Face cell t (face order x-, x+, y-, y+, z-, z+) -> padded coordinates.
+__device__ __forceinline__ Flat face_cell(int64_t u, const Layout& L) {
+    const int64_t nxf = (int64_t)L.nz * L.ny, nyf = (int64_t)L.nz * L.nx, nzf = (int64_t)L.ny * L.nx;
+    Flat f;
+    if (u < 2 * nxf) {
+        int side = (int)(u / nxf);
+        int64_t v = u % nxf;
+        f.k = (int)(v / L.ny);
+        f.j = (int)(v % L.ny);
+        f.i = side ? L.nx : -1;
+    } else if ((u -= 2 * nxf) < 2 * nyf) {
+        int side = (int)(u / nyf);
+        int64_t v = u % nyf;
+        f.k = (int)(v / L.nx);
+        f.i = (int)(v % L.nx);
+        f.j = side ? L.ny : -1;
+    } else {
+        u -= 2 * nyf;
+        int side = (int)(u / nzf);
+        int64_t v = u % nzf;
+        f.j = (int)(v / L.nx);
+        f.i = (int)(v % L.nx);
+        f.k = side ? L.nz : -1;
+    }
+    return f;
+}
+
+template <typename S>
+__global__ void k_faces_out(const S* __restrict__ src, Layout L, S* __restrict__ dst) {
+    const int64_t n = 2 * ((int64_t)L.nz * L.ny + (int64_t)L.nz * L.nx + (int64_t)L.ny * L.nx);
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = face_cell(t, L);
+        dst[t] = src[L.idx(f.i, f.j, f.k)];
+    }
+}
+template <typename S>
+__global__ void k_faces_in(const S* __restrict__ src, Layout L, S* b0, S* b1, S* b2, S* b3) {
+    const int64_t n = 2 * ((int64_t)L.nz * L.ny + (int64_t)L.nz * L.nx + (int64_t)L.ny * L.nx);
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = face_cell(t, L);
+        const int64_t o = L.idx(f.i, f.j, f.k);
+        const S v = src[t];
+        b0[o] = v;
+        b1[o] = v;
+        b2[o] = v;
+        b3[o] = v;
+    }
+}
+
+// Residual partial sums per workgroup: [rr, bb, ss, pp, bad].
+//   r = L_h phi - s,  b = s - (adjacent ghosts)/dx^2,  s = 4 pi G rho.
+constexpr int NRED = 5;
+template <typename S>
+__global__ __launch_bounds__(256) void k_residual_partial(const S* __restrict__ phi, const S* __restrict__ rho,
+                                                          Layout L, double idx2, double four_pi_g,
+                                                          double* __restrict__ partial) {
+    __shared__ double red[4][NRED];
+    double acc[NRED] = {0, 0, 0, 0, 0};
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    HGS_GRID_STRIDE(t, n) {
+        Flat f = unflat(t, L);
+        const int64_t o = L.idx(f.i, f.j, f.k);
+        const double c = (double)phi[o];
+        const double xm = (double)phi[o - 1], xp = (double)phi[o + 1];
+        const double ym = (double)phi[o - L.pitch], yp = (double)phi[o + L.pitch];
+        const double zm = (double)phi[o - L.plane], zp = (double)phi[o + L.plane];
+        double gb = 0.0;
+        if (f.i == 0) gb += xm;
+        if (f.i == L.nx - 1) gb += xp;
+        if (f.j == 0) gb += ym;
+        if (f.j == L.ny - 1) gb += yp;
+        if (f.k == 0) gb += zm;
+        if (f.k == L.nz - 1) gb += zp;
+        const double rv = (double)rho[t];
+        const double s = four_pi_g * rv;
+        const double nb = ((xm + xp) + (ym + yp)) + (zm + zp);
+        const double r = (nb - 6.0 * c) * idx2 - s;
+        const double b = s - gb * idx2;
+        acc[0] += r * r;
+        acc[1] += b * b;
+        acc[2] += s * s;
+        acc[3] += c * c;
+        if (!isfinite(c) || !isfinite(rv)) acc[4] = 1.0;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) {
+        double v = acc[q];
+        if (q == 4) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        } else {
+            v = wave_sum(v);
+        }
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        const int q = threadIdx.x;
+        double v = (q == 4) ? fmax(fmax(red[0][q], red[1][q]), fmax(red[2][q], red[3][q]))
+                            : ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q]));
+        partial[(size_t)blockIdx.x * NRED + q] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_residual_final(const double* __restrict__ partial, int nblocks,
+                                                        double* __restrict__ out) {
+    __shared__ double red[4][NRED];
+    double acc[NRED] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += partial[(size_t)b * NRED + q];
+        acc[4] = fmax(acc[4], partial[(size_t)b * NRED + 4]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NRED; ++q) {
+        double v = acc[q];
+        if (q == 4) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        } else {
+            v = wave_sum(v);
+        }
+        if (lane == 0) red[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        const int q = threadIdx.x;
+        out[q] = (q == 4) ? fmax(fmax(red[0][q], red[1][q]), fmax(red[2][q], red[3][q]))
+                          : ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q]));
+    }
+}
+
+}  // namespace hgs

@@ -1,0 +1,277 @@
+"""Python binding of the C ABI in include/hgs.h (ctypes; argument marshalling only).
+
+Every step of the method runs in the HIP library libhgs.so.  PyTorch supplies
+device memory (the workspace and I/O tensors) and the stream.  If the library
+has not been built, importing this module raises ImportError: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first (python -c 'import __graft_entry__ as g; g.build()')")
+
+# One HIP runtime per process: torch ships its own libamdhip64 (soname
+# libamdhip64.so.7) and loads it by an unversioned name from its own directory.
+# Loading torch first lets libhgs.so's dependency on libamdhip64.so.7 bind to
+# that already-loaded runtime instead of starting a second one, which would
+# find no device once torch's runtime holds it.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+HGS_OK, HGS_ERR_ARG, HGS_ERR_CFL, HGS_ERR_WORKSPACE, HGS_ERR_DEVICE, HGS_ERR_NONFINITE, HGS_ERR_STATE = range(7)
+HGS_F64, HGS_F32 = 0, 1
+HGS_BC_MULTIPOLE, HGS_BC_USER = 0, 1
+TMAX = 8
+LMAX = 4
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+        ("dx", ctypes.c_double), ("G", ctypes.c_double), ("origin", ctypes.c_double * 3),
+        ("lmax", ctypes.c_int32), ("bc", ctypes.c_int32), ("storage", ctypes.c_int32),
+        ("tblock", ctypes.c_int32), ("eta", ctypes.c_double), ("stream", ctypes.c_void_p),
+    ]
+
+
+_vp, _cp, _dp = ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)
+_i32, _dbl, _sz = ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+_CFG = ctypes.POINTER(Config)
+
+_SIGS = {
+    "hgs_config_cube": (_i32, [_CFG, _i32, _dbl, _dbl]),
+    "hgs_workspace_bytes": (_i32, [_CFG, ctypes.POINTER(_sz)]),
+    "hgs_init": (_i32, [_CFG, _vp, _sz, ctypes.POINTER(_vp)]),
+    "hgs_step": (_i32, [_vp, _vp, _dbl, _dbl, _i32]),
+    "hgs_validate_step": (_i32, [_CFG, _vp, _dbl, _dbl, _i32]),
+    "hgs_potential": (_i32, [_vp, _vp, _vp]),
+    "hgs_accel": (_i32, [_vp, _vp, _vp, _vp]),
+    "hgs_set_state": (_i32, [_vp, _vp, _vp, _dbl]),
+    "hgs_set_boundary": (_i32, [_vp, _vp]),
+    "hgs_get_boundary": (_i32, [_vp, _vp]),
+    "hgs_moments": (_i32, [_vp, _dp]),
+    "hgs_residual": (_i32, [_vp, _vp, _dp]),
+    "hgs_save_raw": (_i32, [_vp, _vp, _vp, _dp]),
+    "hgs_load_raw": (_i32, [_vp, _vp, _vp, _dbl]),
+    "hgs_set_tblock": (_i32, [_vp, _i32]),
+    "hgs_get_tblock": (_i32, [_vp]),
+    "hgs_timing_enable": (_i32, [_vp, _i32]),
+    "hgs_timing_read": (_i32, [_vp, _i32, _dp]),
+    "hgs_destroy": (_i32, [_vp]),
+    "hgs_status_str": (_cp, [_i32]),
+    "hgs_last_error": (_cp, [_vp]),
+    "hgs_abi_version": (_i32, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class HGSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.hgs_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+def _check(status: int, ctx=None):
+    if status != HGS_OK:
+        raise HGSError(status, _lib.hgs_last_error(ctx).decode())
+
+
+def library():
+    """The loaded ctypes library (for tests of the raw ABI)."""
+    return _lib
+
+
+def make_config(shape, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, G: float = 1.0,
+                origin=(0.0, 0.0, 0.0), lmax: int = 4, bc: str = "multipole", storage: str = "f32",
+                tblock: int = 0, eta: float = 0.0, stream: int = 0) -> Config:
+    """shape = (nz, ny, nx) or n; default dx spans [-1, 1] along x."""
+    nz, ny, nx = (shape, shape, shape) if np.isscalar(shape) else shape
+    c = Config()
+    c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
+    c.x0, c.y0, c.z0 = (float(v) for v in x0)
+    c.dx = float(dx) if dx is not None else 2.0 / nx
+    c.G = float(G)
+    c.origin = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    c.lmax = int(lmax)
+    c.bc = {"multipole": HGS_BC_MULTIPOLE, "user": HGS_BC_USER}[bc]
+    c.storage = {"f64": HGS_F64, "f32": HGS_F32}[storage]
+    c.tblock = int(tblock)
+    c.eta = float(eta)
+    c.stream = int(stream) or None
+    return c
+
+
+def workspace_bytes(cfg: Config) -> int:
+    n = _sz(0)
+    _check(_lib.hgs_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)))
+    return n.value
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Solver:
+    """One grid; all tensors live on the CUDA (HIP) device in the storage dtype."""
+
+    def __init__(self, shape, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, G: float = 1.0,
+                 origin=(0.0, 0.0, 0.0), lmax: int = 4, bc: str = "multipole", storage: str = "f32",
+                 tblock: int = 0, eta: float = 0.0, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.dtype = torch.float32 if storage == "f32" else torch.float64
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.cfg = make_config(shape, x0, dx, G, origin, lmax, bc, storage, tblock, eta, self.stream.cuda_stream)
+        self.shape = (self.cfg.nz, self.cfg.ny, self.cfg.nx)
+        nbytes = workspace_bytes(self.cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_lib.hgs_init(ctypes.byref(self.cfg), self.workspace.data_ptr(), nbytes, ctypes.byref(h)))
+        self._h = h
+
+    # -- helpers
+    def _need(self, t, shape=None):
+        shape = self.shape if shape is None else shape
+        if t is None:
+            return None
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected a contiguous {self.dtype} tensor of shape {shape} on {self.device}")
+        return t
+
+    def _new(self, shape=None):
+        return self.torch.empty(self.shape if shape is None else shape, dtype=self.dtype, device=self.device)
+
+    @property
+    def face_count(self) -> int:
+        nz, ny, nx = self.shape
+        return 2 * (nz * ny + nz * nx + ny * nx)
+
+    @property
+    def dx(self) -> float:
+        return self.cfg.dx
+
+    # -- API
+    def step(self, rho, c_g: float, dt: float, nsub: int) -> None:
+        self._need(rho)
+        _check(_lib.hgs_step(self._h, rho.data_ptr(), float(c_g), float(dt), int(nsub)), self._h)
+
+    def potential(self, with_phidot: bool = True):
+        phi = self._new()
+        pd = self._new() if with_phidot else None
+        _check(_lib.hgs_potential(self._h, phi.data_ptr(), _ptr(pd)), self._h)
+        return phi, pd
+
+    def accel(self, out=None):
+        g = [self._new() for _ in range(3)] if out is None else [self._need(t) for t in out]
+        _check(_lib.hgs_accel(self._h, *(t.data_ptr() for t in g)), self._h)
+        return tuple(g)
+
+    def set_state(self, phi, phidot, dt: float) -> None:
+        self._need(phi)
+        self._need(phidot)
+        _check(_lib.hgs_set_state(self._h, phi.data_ptr(), _ptr(phidot), float(dt)), self._h)
+
+    def set_boundary(self, ghosts) -> None:
+        self._need(ghosts, (self.face_count,))
+        _check(_lib.hgs_set_boundary(self._h, ghosts.data_ptr()), self._h)
+
+    def get_boundary(self):
+        out = self._new((self.face_count,))
+        _check(_lib.hgs_get_boundary(self._h, out.data_ptr()), self._h)
+        return out
+
+    def moments(self) -> np.ndarray:
+        n = (self.cfg.lmax + 1) ** 2
+        buf = (ctypes.c_double * (2 * n))()
+        _check(_lib.hgs_moments(self._h, buf), self._h)
+        a = np.frombuffer(buf, dtype=np.float64).copy()
+        return a[0::2] + 1j * a[1::2]
+
+    def residual(self, rho) -> np.ndarray:
+        """[R_b, R_f, ||phi||, nonfinite]; raises HGSError(HGS_ERR_NONFINITE) on NaN/Inf."""
+        self._need(rho)
+        out = (ctypes.c_double * 4)()
+        st = _lib.hgs_residual(self._h, rho.data_ptr(), out)
+        res = np.frombuffer(out, dtype=np.float64).copy()
+        if st == HGS_ERR_NONFINITE:
+            err = HGSError(st, _lib.hgs_last_error(self._h).decode())
+            err.values = res
+            raise err
+        _check(st, self._h)
+        return res
+
+    def save_raw(self):
+        a, b = self._new(), self._new()
+        dtp = ctypes.c_double(0.0)
+        _check(_lib.hgs_save_raw(self._h, a.data_ptr(), b.data_ptr(), ctypes.byref(dtp)), self._h)
+        return a, b, dtp.value
+
+    def load_raw(self, phi_n, phi_nm1, dt_prev: float) -> None:
+        self._need(phi_n)
+        self._need(phi_nm1)
+        _check(_lib.hgs_load_raw(self._h, phi_n.data_ptr(), phi_nm1.data_ptr(), float(dt_prev)), self._h)
+
+    KERNEL_KINDS = {"stencil": 0, "multipole": 1, "gradient": 2}
+
+    def timing(self, enable: bool) -> None:
+        _check(_lib.hgs_timing_enable(self._h, int(bool(enable))), self._h)
+
+    def timing_read(self, kind: str = "stencil") -> dict:
+        out = (ctypes.c_double * 4)()
+        _check(_lib.hgs_timing_read(self._h, self.KERNEL_KINDS[kind], out), self._h)
+        n, ms, nbytes, upd = list(out)
+        return {"launches": int(n), "ms": ms, "bytes": nbytes, "updates": upd}
+
+    def set_tblock(self, t: int) -> None:
+        _check(_lib.hgs_set_tblock(self._h, int(t)), self._h)
+
+    @property
+    def tblock(self) -> int:
+        return int(_lib.hgs_get_tblock(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.hgs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def faces_to_flat(face_list: Sequence) -> np.ndarray:
+    """Concatenate six face arrays (x-, x+, y-, y+, z-, z+) into the flat ghost layout."""
+    return np.concatenate([np.asarray(f).ravel() for f in face_list])
+
+
+def flat_to_faces(flat, shape):
+    nz, ny, nx = shape
+    sizes = [nz * ny, nz * ny, nz * nx, nz * nx, ny * nx, ny * nx]
+    shapes = [(nz, ny), (nz, ny), (nz, nx), (nz, nx), (ny, nx), (ny, nx)]
+    out, o = [], 0
+    for s, sh in zip(sizes, shapes):
+        out.append(np.asarray(flat[o:o + s]).reshape(sh))
+        o += s
+    return out

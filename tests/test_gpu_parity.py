@@ -1,0 +1,358 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances: FP64 storage 1e-10 relative (max-norm relative per field), FP32
+storage 1e-4 relative to the FP64 oracle, and 2e-6 relative to the oracle's
+binary32-storage emulation (same rounding points, FP64 arithmetic).  Shapes
+include a single cell, tiny ragged boxes and grids that span several tiles
+with ragged tails in every direction.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import analytic, poisson
+from oracle.core import Grid, Oracle
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+F32_TOL = 1e-4
+F32_EMU_TOL = 2e-6
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+def grid_of(shape):
+    """Box centred on the origin (the multipole centre), dx = 2 / max(shape)."""
+    nz, ny, nx = shape
+    dx = 2.0 / max(shape)
+    return Grid(nx, ny, nz, -0.5 * nx * dx, -0.5 * ny * dx, -0.5 * nz * dx, dx)
+
+
+def corner(shape):
+    g = grid_of(shape)
+    return (g.x0, g.y0, g.z0)
+
+
+def npdt(storage):
+    return np.float64 if storage == "f64" else np.float32
+
+
+def dens(shape, seed, storage, k=6, blobs=None):
+    g = grid_of(shape)
+    x, y, z = workloads.centred_axes(shape, g.dx)
+    b = workloads.blob_params(seed, k) if blobs is None else blobs
+    return workloads.blob_density_axes(x, y, z, b, dtype=npdt(storage))
+
+
+def to_dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def solver(hgs, shape, **kw):
+    g = grid_of(shape)
+    return hgs.Solver(shape, x0=corner(shape), dx=g.dx, **kw)
+
+
+def pair(hgs, shape, storage="f64", lmax=4, eta=0.0, origin=(0.0, 0.0, 0.0), bc="multipole", tblock=0):
+    s = solver(hgs, shape, storage=storage, lmax=lmax, eta=eta, origin=origin, bc=bc, tblock=tblock)
+    o = Oracle(grid_of(shape), lmax=lmax, eta=eta, origin=origin, bc=bc)
+    return s, o
+
+
+SHAPES = [(1, 1, 1), (3, 2, 5), (7, 9, 4), (23, 29, 37), (40, 33, 130), (64, 64, 64)]
+
+
+# ------------------------------------------------------------------ multipole moments and ghosts
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 6, 7), (23, 29, 37), (70, 9, 66), (64, 64, 64)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("origin", [(0.0, 0.0, 0.0), (0.1, -0.07, 0.05)])
+def test_moments_and_ghosts(gpu_lib, shape, storage, origin):
+    rho = dens(shape, 11, storage)
+    g = grid_of(shape)
+    for lmax in (0, 2, 4):
+        s, o = pair(gpu_lib, shape, storage, lmax=lmax, origin=origin)
+        s.step(to_dev(rho), 1.0, 0.1 * g.dx, 1)
+        q = s.moments()
+        from oracle import core
+
+        qo = core.moments(g, rho.astype(np.float64), lmax, origin)
+        assert q.shape == qo.shape
+        assert np.max(np.abs(q - qo)) <= 1e-12 * np.max(np.abs(qo)), (lmax, q, qo)
+        P = core.padded(g)
+        core.boundary(g, qo, lmax, 1.0, P, origin)
+        want = gpu_lib.faces_to_flat(core.faces(P))
+        got = host(s.get_boundary())
+        tol = 1e-12 if storage == "f64" else 1e-7
+        assert rel(got, want) < tol, lmax
+
+
+def test_moments_match_legendre_brute_force(gpu_lib):
+    """The GPU ghost shell against the addition theorem summed over cells."""
+    shape = (9, 11, 10)
+    g = grid_of(shape)
+    rho = workloads.random_field(shape, 4, 0.0, 1.0)
+    s = solver(gpu_lib, shape, storage="f64", lmax=4, origin=(0.05, 0.02, -0.03))
+    s.step(to_dev(rho), 1.0, 0.1 * g.dx, 1)
+    got = gpu_lib.flat_to_faces(host(s.get_boundary()), shape)
+    for f, pts in zip(got, analytic.ghost_points(g)):
+        want = analytic.legendre_multipole(g, rho, pts, 4, 1.0, (0.05, 0.02, -0.03))
+        assert rel(f.ravel(), want) < 1e-12
+
+
+# ------------------------------------------------------------------ leapfrog + gradient
+
+def compare_state(s, o, storage, tol):
+    phi, pd = s.potential()
+    rp, rpd = o.potential()
+    e_phi = rel(host(phi), rp)
+    # phidot = (phi^n - phi^{n-1})/dt: an eps-relative error in phi shows up as
+    # eps |phi| / dt, so near a converged state (phidot ~ rounding noise) its
+    # error is measured on that scale
+    e_pd = min(rel(host(pd), rpd), float(np.max(np.abs(host(pd) - rpd))) * o.dt_prev / np.max(np.abs(rp)))
+    gx, gy, gz = s.accel()
+    ro = o.accel()
+    e_g = max(rel(host(a), b) for a, b in zip((gx, gy, gz), ro))
+    assert e_phi < tol and e_pd < tol * 10 and e_g < tol * 10, (e_phi, e_pd, e_g)
+    return e_phi, e_pd, e_g
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("eta", [0.0, 3.0])
+def test_leapfrog_f64(gpu_lib, shape, eta):
+    rho = dens(shape, 5, "f64")
+    g = grid_of(shape)
+    s, o = pair(gpu_lib, shape, "f64", eta=eta)
+    dt = 0.4 * g.dx
+    for nsub in (1, 7, 30):
+        s.step(to_dev(rho), 1.0, dt, nsub)
+        o.step(rho, 1.0, dt, nsub)
+    compare_state(s, o, "f64", F64_TOL)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_leapfrog_f32(gpu_lib, shape):
+    rho = dens(shape, 6, "f32")
+    r64 = rho.astype(np.float64)
+    g = grid_of(shape)
+    s, o = pair(gpu_lib, shape, "f32", eta=1.0)
+    emu = Oracle(g, lmax=4, eta=1.0, storage="f32")
+    dt = 0.4 * g.dx
+    for nsub in (4, 4, 13):
+        s.step(to_dev(rho), 1.0, dt, nsub)
+        o.step(r64, 1.0, dt, nsub)
+        emu.step(r64, 1.0, dt, nsub)
+    compare_state(s, o, "f32", F32_TOL)
+    phi, _ = s.potential()
+    assert rel(host(phi), emu.potential()[0]) < F32_EMU_TOL
+
+
+def test_moving_density_and_dt_changes(gpu_lib):
+    """rho changes every hydro step (a rotating blob mixture) and dt changes:
+    phi^{n-1} is rescaled to keep (phi^n - phi^{n-1})/dt."""
+    shape = (33, 40, 36)
+    g = grid_of(shape)
+    base = workloads.blob_params(8, 5)
+    s, o = pair(gpu_lib, shape, "f64", eta=0.0)
+    for h, (dt, nsub) in enumerate([(0.4, 4), (0.4, 4), (0.3, 5), (0.5, 3), (0.5, 4), (0.2, 9)]):
+        rho = dens(shape, 0, "f64", blobs=base.rotated(0.05 * h))
+        s.step(to_dev(rho), 1.0, dt * g.dx, nsub)
+        o.step(rho, 1.0, dt * g.dx, nsub)
+    compare_state(s, o, "f64", F64_TOL)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_set_state_then_step(gpu_lib, storage):
+    shape = (20, 18, 22)
+    g = grid_of(shape)
+    rng = np.random.default_rng(3)
+    phi0 = rng.uniform(-2, -1, shape).astype(npdt(storage))
+    pd0 = rng.uniform(-0.1, 0.1, shape).astype(npdt(storage))
+    rho = dens(shape, 9, storage)
+    s = solver(gpu_lib, shape, storage=storage, eta=0.5)
+    o = Oracle(g, eta=0.5, storage=storage)
+    s.set_state(to_dev(phi0), to_dev(pd0), 0.35 * g.dx)
+    o.set_state(phi0.astype(np.float64), pd0.astype(np.float64), 0.35 * g.dx)
+    p, d = s.potential()
+    assert np.array_equal(host(p), phi0.astype(np.float64))
+    s.step(to_dev(rho), 1.0, 0.4 * g.dx, 6)
+    o.step(rho.astype(np.float64), 1.0, 0.4 * g.dx, 6)
+    phi, _ = s.potential()
+    assert rel(host(phi), o.potential()[0]) < (F64_TOL if storage == "f64" else F32_EMU_TOL)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_checkpoint_resume_bitwise(gpu_lib, storage):
+    """2N substeps equal N, save, restore into a fresh context, N more -- bitwise."""
+    import torch
+
+    shape = (30, 31, 29)
+    g = grid_of(shape)
+    rho = to_dev(dens(shape, 2, storage))
+    a = solver(gpu_lib, shape, storage=storage, eta=0.2)
+    for _ in range(4):
+        a.step(rho, 1.0, 0.4 * g.dx, 5)
+    b = solver(gpu_lib, shape, storage=storage, eta=0.2)
+    for _ in range(2):
+        b.step(rho, 1.0, 0.4 * g.dx, 5)
+    pn, pm, dtp = b.save_raw()
+    c = solver(gpu_lib, shape, storage=storage, eta=0.2)
+    c.load_raw(pn, pm, dtp)
+    for _ in range(2):
+        c.step(rho, 1.0, 0.4 * g.dx, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(a.potential()[0], c.potential()[0])
+    assert torch.equal(a.save_raw()[1], c.save_raw()[1])
+
+
+def test_user_boundary_direct_sum(gpu_lib):
+    """bc = USER with ghosts from the free-space direct sum, damped relaxation."""
+    shape = (16, 16, 16)
+    g = grid_of(shape)
+    rho = workloads.gaussian_density(16, 0.2, 1.0, (0.1, -0.05, 0.0))
+    from oracle import core
+
+    faces = [analytic.direct_sum_points(g, rho, p).reshape(f.shape)
+             for p, f in zip(analytic.ghost_points(g), core.faces(core.padded(g)))]
+    eta = 2.0 * math.sqrt(poisson.lambda_min(g))
+    s, o = pair(gpu_lib, shape, "f64", eta=eta, bc="user")
+    s.set_boundary(to_dev(gpu_lib.faces_to_flat(faces)))
+    o.set_boundary(faces)
+    s.step(to_dev(rho), 1.0, 0.4 * g.dx, 300)
+    o.step(rho, 1.0, 0.4 * g.dx, 300)
+    compare_state(s, o, "f64", F64_TOL)
+    assert np.array_equal(host(s.get_boundary()), gpu_lib.faces_to_flat(faces))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_residual_norms(gpu_lib, storage):
+    shape = (21, 26, 19)
+    g = grid_of(shape)
+    rho = dens(shape, 4, storage)
+    s, o = pair(gpu_lib, shape, storage, eta=2.0)
+    r0 = s.residual(to_dev(rho))
+    assert r0[0] == pytest.approx(1.0, rel=1e-14)  # phi = 0 and zero ghosts: r = -s = -b
+    s.step(to_dev(rho), 1.0, 0.4 * g.dx, 40)
+    o.step(rho.astype(np.float64), 1.0, 0.4 * g.dx, 40)
+    r = s.residual(to_dev(rho))
+    # compare against the oracle residual of the GPU's own state (norm definitions)
+    from oracle import core
+
+    P = o.Pn.copy()
+    core.interior(P)[...] = host(s.potential()[0])
+    core.set_faces(P, gpu_lib.flat_to_faces(host(s.get_boundary()), shape))
+    want = core.residual(g, P, rho.astype(np.float64), 1.0)
+    assert np.allclose(r[:3], want[:3], rtol=1e-10, atol=0)
+    assert r[3] == 0.0
+
+
+def test_nonfinite_detected(gpu_lib):
+    shape = (8, 9, 10)
+    rho = dens(shape, 1, "f64")
+    s = solver(gpu_lib, shape, storage="f64")
+    s.step(to_dev(rho), 1.0, 0.01, 2)
+    bad = rho.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(gpu_lib.HGSError) as ei:
+        s.residual(to_dev(bad))
+    assert ei.value.status == gpu_lib.HGS_ERR_NONFINITE
+
+
+def test_errors_leave_state_unchanged(gpu_lib):
+    import torch
+
+    shape = (12, 12, 12)
+    g = grid_of(shape)
+    rho = to_dev(dens(shape, 3, "f64"))
+    s = solver(gpu_lib, shape, storage="f64")
+    with pytest.raises(gpu_lib.HGSError) as ei:
+        s.moments()
+    assert ei.value.status == gpu_lib.HGS_ERR_STATE
+    s.step(rho, 1.0, 0.4 * g.dx, 3)
+    before = s.save_raw()
+    with pytest.raises(gpu_lib.HGSError) as ei:
+        s.step(rho, 1.0, 0.6 * g.dx, 3)
+    assert ei.value.status == gpu_lib.HGS_ERR_CFL
+    with pytest.raises(gpu_lib.HGSError) as ei:
+        s.step(rho, 1.0, 0.4 * g.dx, 0)
+    assert ei.value.status == gpu_lib.HGS_ERR_ARG
+    with pytest.raises(gpu_lib.HGSError) as ei:
+        s.set_boundary(torch.zeros(s.face_count, dtype=torch.float64, device="cuda"))
+    assert ei.value.status == gpu_lib.HGS_ERR_STATE
+    after = s.save_raw()
+    assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1]) and before[2] == after[2]
+
+
+# ------------------------------------------------------------------ the paper-sized workloads
+
+@pytest.mark.parametrize("eta_mode", ["paper", "critical"])
+def test_uniform_sphere_64_2000_steps(gpu_lib, eta_mode):
+    """64^3 on [-1,1]^3, sphere rho = 1 for r < 1/4, G = c_g = 1, dt = 0.4 dx,
+    zero start, monopole boundary -G M_h / r, 2000 substeps, FP64."""
+    n = 64
+    g = Grid.cube(n)
+    rho = workloads.sphere_density(n, 0.25)
+    eta = 0.0 if eta_mode == "paper" else 2.0 * math.sqrt(poisson.lambda_min(g))
+    s, o = pair(gpu_lib, (n, n, n), "f64", lmax=0, eta=eta)
+    dt = 0.4 * g.dx
+    s.step(to_dev(rho), 1.0, dt, 2000)
+    o.step(rho, 1.0, dt, 2000)
+    compare_state(s, o, "f64", F64_TOL)
+    if eta_mode == "critical":
+        phi = host(s.potential()[0])
+        dst = poisson.solve_dst(g, rho, 1.0, o.Pn)
+        assert rel(phi, dst) < 1e-12
+        X, Y, Z = analytic.cell_centres(g)
+        exact = analytic.sphere_potential(np.sqrt(X * X + Y * Y + Z * Z), 4 * np.pi * 0.25 ** 3 / 3, 0.25)
+        err = np.linalg.norm(phi - exact) / np.linalg.norm(exact)
+        assert 0.005 < err < 0.03  # the staircase mass (+1.5%) dominates
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_full_size_512_f32_two_hydro_steps(gpu_lib):
+    """The benchmarked configuration: 512^3, FP32 storage, 16 blobs, lmax 4,
+    4 substeps per hydro step, in the launch configuration the benchmark uses,
+    compared over every cell with the FP64 oracle.  The start is a smooth
+    non-zero potential so that every stencil term carries weight."""
+    import torch
+
+    n = 512
+    g = Grid.cube(n)
+    blobs = workloads.blob_params(1, 16)
+    rho = workloads.blob_density_torch(n, blobs, "cuda", torch.float32)
+    ax = -1.0 + (torch.arange(n, device="cuda", dtype=torch.float64) + 0.5) * g.dx
+    r2 = ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+    phi0 = (-1.0 / torch.sqrt(r2 + 0.09)).to(torch.float32)
+    s = gpu_lib.Solver(n, storage="f32", lmax=4, eta=0.0)
+    dt = 0.4 * g.dx
+    s.set_state(phi0, None, dt)
+    for h in range(2):
+        s.step(rho, 1.0, dt, 4)
+    phi, pd = s.potential()
+    gx, gy, gz = s.accel()
+    r64 = host(rho)
+    o = Oracle(g, lmax=4, eta=0.0)
+    o.set_state(host(phi0), None, dt)
+    del phi0, r2
+    for h in range(2):
+        o.step(r64, 1.0, dt, 4)
+    rp, rpd = o.potential()
+    assert rel(host(phi), rp) < F32_TOL
+    assert rel(host(pd), rpd) < 10 * F32_TOL
+    for a, b in zip((gx, gy, gz), o.accel()):
+        assert rel(host(a), b) < 10 * F32_TOL

@@ -47,21 +47,33 @@ def axis(n: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     return lo + (np.arange(n) + 0.5) * dx
 
 
-def blob_density(n, blobs: Blobs, lo: float = -1.0, hi: float = 1.0, dtype=np.float64) -> np.ndarray:
-    """rho on an n^3 (or (nz,ny,nx) tuple) cell-centred grid over [lo,hi]^3,
-    shape (nz, ny, nx).  Each Gaussian is a product of three 1D factors."""
-    nz, ny, nx = (n, n, n) if np.isscalar(n) else n
-    dx = (hi - lo) / nx
-    x = lo + (np.arange(nx) + 0.5) * dx
-    y = lo + (np.arange(ny) + 0.5) * dx
-    z = lo + (np.arange(nz) + 0.5) * dx
-    rho = np.zeros((nz, ny, nx))
+def blob_density_axes(x: np.ndarray, y: np.ndarray, z: np.ndarray, blobs: Blobs, dtype=np.float64) -> np.ndarray:
+    """rho at the cell centres x (nx,), y (ny,), z (nz,); shape (nz, ny, nx).
+    Each Gaussian is a product of three 1D factors."""
+    rho = np.zeros((len(z), len(y), len(x)))
     for c, s, a in zip(blobs.centres, blobs.sigma, blobs.amp):
         fx = np.exp(-((x - c[0]) ** 2) / (2 * s * s))
         fy = np.exp(-((y - c[1]) ** 2) / (2 * s * s))
         fz = np.exp(-((z - c[2]) ** 2) / (2 * s * s))
         rho += a * fz[:, None, None] * (fy[:, None] * fx[None, :])[None, :, :]
     return rho.astype(dtype)
+
+
+def centred_axes(shape, dx: float):
+    """Cell-centre axes of a (nz, ny, nx) box of cell size dx centred on the origin."""
+    nz, ny, nx = shape
+    return tuple((np.arange(m) + 0.5) * dx - 0.5 * m * dx for m in (nx, ny, nz))
+
+
+def blob_density(n, blobs: Blobs, lo: float = -1.0, hi: float = 1.0, dtype=np.float64) -> np.ndarray:
+    """rho on an n^3 (or (nz,ny,nx) tuple) cell-centred grid with lower corner lo
+    on every axis and dx = (hi - lo) / nx, shape (nz, ny, nx)."""
+    nz, ny, nx = (n, n, n) if np.isscalar(n) else n
+    dx = (hi - lo) / nx
+    x = lo + (np.arange(nx) + 0.5) * dx
+    y = lo + (np.arange(ny) + 0.5) * dx
+    z = lo + (np.arange(nz) + 0.5) * dx
+    return blob_density_axes(x, y, z, blobs, dtype)
 
 
 def blob_density_torch(n: int, blobs: Blobs, device, dtype, lo: float = -1.0, hi: float = 1.0):
