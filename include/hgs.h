@@ -69,7 +69,7 @@ typedef enum {
 } hgs_bc;
 
 /* Largest temporal-blocking depth (substeps fused per launch). */
-#define HGS_TMAX 8
+#define HGS_TMAX 4
 /* Largest multipole degree. */
 #define HGS_LMAX 4
 

@@ -3,13 +3,12 @@
 // Padded field layout in HBM (one per state buffer):
 //   x: interior cell i at element xoff + i of a row; xoff is 128 bytes worth of
 //      elements so every interior row starts on a 128-byte line; the row pitch
-//      is a multiple of 128 bytes with at least HALO spare elements on each side;
-//   y: HALO rows below and above the interior;  z: HALO planes below and above.
-// Ghost cells (the Dirichlet boundary) are the layer adjacent to each face.
-// Everything else outside the interior is padding that no update reads; it
-// lets an extended tile of a temporally blocked launch be loaded without
-// bounds checks.  Padding is filled with NaN at init so that an erroneous
-// read poisons the result instead of passing silently.
+//      is a multiple of 128 bytes with room for a 16-byte vector at x = nx;
+//   y: one row below and above the interior;  z: one plane below and above.
+// Ghost cells (the Dirichlet boundary) are that layer adjacent to each face;
+// edges, corners and the rest of each row are padding that no update reads.
+// Padding is filled with NaN at init so that an erroneous read poisons the
+// result instead of passing silently.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,7 +18,7 @@
 
 namespace hgs {
 
-constexpr int HALO = HGS_TMAX;  // spare rows/planes around the interior
+constexpr int HALO = 1;  // ghost rows/planes around the interior
 constexpr int NQ = (HGS_LMAX + 1) * (HGS_LMAX + 1);  // 25 multipole coefficients
 
 struct Layout {
@@ -41,8 +40,9 @@ inline Layout make_layout(int nx, int ny, int nz, int elem_bytes) {
     L.ny = ny;
     L.nz = nz;
     const int line = 128 / elem_bytes;
-    L.xoff = line;  // >= HALO for 4- and 8-byte elements
-    int need = L.xoff + nx + HALO;
+    L.xoff = line;
+    // the ghost cell plus room for one 16-byte vector starting at x = nx
+    int need = L.xoff + nx + 4;
     L.pitch = (need + line - 1) / line * line;
     L.rows = ny + 2 * HALO;
     L.plane = (int64_t)L.pitch * L.rows;

@@ -33,12 +33,14 @@ struct hgs_ctx {
     double* mom_partial;
     double* mom;
     int mom_blocks, mom_zc, mom_tx, mom_ty;
+    bool mom_vec;  // 16-byte loads along x (nx a multiple of the vector width)
     double* red_partial;
     double* red_out;
     int red_blocks;
     double dt_prev;
     bool have_moments;
     int tblock;
+    int ncu;  // compute units of the device
     std::string err;
     // launch timing (hgs_timing_*)
     bool timing;
@@ -74,6 +76,7 @@ struct Plan {
     size_t buf_bytes;  // one padded state buffer
     size_t mom_partial_off, mom_off, red_partial_off, red_out_off, total;
     int mom_blocks, mom_zc, mom_tx, mom_ty;
+    bool mom_vec;
 };
 
 hgs_status check_config(const hgs_config* cfg, std::string& why) {
@@ -107,7 +110,7 @@ hgs_status check_config(const hgs_config* cfg, std::string& why) {
         return HGS_ERR_ARG;
     }
     if (cfg->tblock < 0 || cfg->tblock > HGS_TMAX) {
-        why = "tblock must be in 0..8";
+        why = "tblock must be in 0..4";
         return HGS_ERR_ARG;
     }
     if (!(cfg->eta >= 0.0) || !std::isfinite(cfg->eta)) {
@@ -139,8 +142,12 @@ Plan make_plan(const hgs_config* cfg) {
     int es = cfg->storage == HGS_F64 ? 8 : 4;
     Layout L = make_layout(cfg->nx, cfg->ny, cfg->nz, es);
     p.buf_bytes = align_up((size_t)L.total * es, kAlign);
-    // moments: 64 x 4 column tiles; split z so that there are >= 2048 workgroups when possible
-    p.mom_tx = (cfg->nx + 63) / 64;
+    // moments: 64 x 4 lanes over (x, y) columns (N columns per lane when
+    // vectorised); split z so that there are >= 2048 workgroups when possible
+    const int vec = 16 / es;
+    p.mom_vec = cfg->nx % vec == 0;
+    const int colw = p.mom_vec ? 64 * vec : 64;
+    p.mom_tx = (cfg->nx + colw - 1) / colw;
     p.mom_ty = (cfg->ny + 3) / 4;
     int cols = p.mom_tx * p.mom_ty;
     int zsplit = std::max(1, std::min(cfg->nz, (2048 + cols - 1) / cols));
@@ -238,17 +245,23 @@ struct Timed {
 
 // ---- launches, templated on the storage type ---------------------------------
 
-constexpr int SBX = 64, SBY = 4;  // streaming tile
+constexpr int SBX = 64, SBY = 4;  // streaming tile (scalar kernels)
 
-template <typename S>
-void stream_dims(const Layout& L, int& zc, int& tiles_x, int& tiles_y, int& nblocks) {
-    tiles_x = (L.nx + SBX - 1) / SBX;
+// Tiles of bx x SBY columns marching up z chunks of >= 16 planes, with enough
+// workgroups to fill every CU several times over.
+inline void stream_dims(const Layout& L, int bx, int& zc, int& tiles_x, int& tiles_y, int& nblocks) {
+    tiles_x = (L.nx + bx - 1) / bx;
     tiles_y = (L.ny + SBY - 1) / SBY;
     int cols = tiles_x * tiles_y;
-    // enough workgroups to fill 256 CUs several times over, z chunks >= 16 planes
     int zsplit = std::max(1, std::min((L.nz + 15) / 16, (4096 + cols - 1) / cols));
     zc = (L.nz + zsplit - 1) / zsplit;
     nblocks = cols * ((L.nz + zc - 1) / zc);
+}
+
+// the 16-byte-per-lane kernels need whole vectors along x
+template <typename S>
+bool use_vec(const Layout& L) {
+    return L.nx % Vec16<S>::N == 0;
 }
 
 template <typename S>
@@ -256,13 +269,18 @@ void run_moments_and_ghosts(hgs_ctx* c, const void* rho) {
     const MomGeom g = geom(c);
     Timed tm(c, HGS_KERNEL_MULTIPOLE);
     dim3 blk(64, 4);
-    hipLaunchKernelGGL(k_moments_partial<S>, dim3(c->mom_blocks), blk, 0, c->stream, static_cast<const S*>(rho), g,
-                       c->mom_zc, c->mom_tx, c->mom_ty, c->mom_partial);
+    if (c->mom_vec)
+        hipLaunchKernelGGL(k_moments_partial_v<S>, dim3(c->mom_blocks), blk, 0, c->stream,
+                           static_cast<const S*>(rho), g, c->mom_zc, c->mom_tx, c->mom_ty, c->mom_partial);
+    else
+        hipLaunchKernelGGL(k_moments_partial<S>, dim3(c->mom_blocks), blk, 0, c->stream, static_cast<const S*>(rho),
+                           g, c->mom_zc, c->mom_tx, c->mom_ty, c->mom_partial);
     hipLaunchKernelGGL(k_moments_final, dim3(NQ), dim3(256), 0, c->stream, c->mom_partial, c->mom_blocks,
                        c->cfg.dx * c->cfg.dx * c->cfg.dx, c->mom);
     const int64_t nf = 2 * ((int64_t)c->L.nz * c->L.ny + (int64_t)c->L.nz * c->L.nx + (int64_t)c->L.ny * c->L.nx);
-    hipLaunchKernelGGL(k_ghosts<S>, dim3(grid_for(nf)), dim3(256), 0, c->stream, c->L, g, c->cfg.lmax, c->cfg.G,
-                       c->mom, B<S>(c, 0), B<S>(c, 1), B<S>(c, 2), B<S>(c, 3));
+    const int maxfast = std::max(c->L.nx, c->L.ny), maxslow = std::max(c->L.ny, c->L.nz);
+    hipLaunchKernelGGL(k_ghosts<S>, dim3((maxfast + 255) / 256, maxslow, 6), dim3(256), 0, c->stream, c->L, g,
+                       c->cfg.lmax, c->cfg.G, c->mom, B<S>(c, 0), B<S>(c, 1), B<S>(c, 2), B<S>(c, 3));
     tm.end((double)sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz + 4.0 * sizeof(S) * (double)nf, 0.0);
 }
 
@@ -271,7 +289,7 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub) {
     const S* r = static_cast<const S*>(rho);
     int T = c->tblock;
     while (nsub > 0) {
-        if (kTBlockAvailable && T > 1 && nsub >= T) {
+        if (T > 1 && nsub >= T) {
             // out of place: (cur, old) -> (the other two buffers)
             int o0 = -1, o1 = -1;
             for (int k = 0; k < 4; ++k)
@@ -282,7 +300,8 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub) {
                         o1 = k;
                 }
             Timed tm(c, HGS_KERNEL_STENCIL);
-            launch_tblock<S>(B<S>(c, c->cur), B<S>(c, c->old), r, B<S>(c, o0), B<S>(c, o1), c->L, sc, T, c->stream);
+            launch_tblock<S>(B<S>(c, c->cur), B<S>(c, c->old), r, B<S>(c, o0), B<S>(c, o1), c->L, sc, T, c->ncu,
+                             c->stream);
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(5.0 * sizeof(S) * cells, cells * T);
             c->cur = o0;
@@ -290,10 +309,16 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub) {
             nsub -= T;
         } else {
             int zc, tx, ty, nb;
-            stream_dims<S>(c->L, zc, tx, ty, nb);
             Timed tm(c, HGS_KERNEL_STENCIL);
-            hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream,
-                               B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty);
+            if (use_vec<S>(c->L)) {
+                stream_dims(c->L, 64 * Vec16<S>::N, zc, tx, ty, nb);
+                hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream,
+                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty);
+            } else {
+                stream_dims(c->L, SBX, zc, tx, ty, nb);
+                hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream,
+                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty);
+            }
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(4.0 * sizeof(S) * cells, cells);
             std::swap(c->cur, c->old);
@@ -305,10 +330,18 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub) {
 template <typename S>
 void run_accel(hgs_ctx* c, void* gx, void* gy, void* gz) {
     int zc, tx, ty, nb;
-    stream_dims<S>(c->L, zc, tx, ty, nb);
     Timed tm(c, HGS_KERNEL_GRADIENT);
-    hipLaunchKernelGGL((k_gradient<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream, B<S>(c, c->cur), c->L,
-                       0.5 / c->cfg.dx, zc, tx, ty, static_cast<S*>(gx), static_cast<S*>(gy), static_cast<S*>(gz));
+    if (use_vec<S>(c->L)) {
+        stream_dims(c->L, 64 * Vec16<S>::N, zc, tx, ty, nb);
+        hipLaunchKernelGGL((k_gradient_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream, B<S>(c, c->cur), c->L,
+                           0.5 / c->cfg.dx, zc, tx, ty, static_cast<S*>(gx), static_cast<S*>(gy),
+                           static_cast<S*>(gz));
+    } else {
+        stream_dims(c->L, SBX, zc, tx, ty, nb);
+        hipLaunchKernelGGL((k_gradient<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream, B<S>(c, c->cur),
+                           c->L, 0.5 / c->cfg.dx, zc, tx, ty, static_cast<S*>(gx), static_cast<S*>(gy),
+                           static_cast<S*>(gz));
+    }
     tm.end(4.0 * sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz, 0.0);
 }
 
@@ -365,9 +398,18 @@ void run_faces_out(hgs_ctx* c, void* dst) {
 template <typename S>
 void run_residual(hgs_ctx* c, const void* rho) {
     const double idx2 = 1.0 / (c->cfg.dx * c->cfg.dx);
-    int nb = grid_for(ncell(c), 256, kRedBlocks);
-    hipLaunchKernelGGL(k_residual_partial<S>, dim3(nb), dim3(256), 0, c->stream, B<S>(c, c->cur),
-                       static_cast<const S*>(rho), c->L, idx2, 4.0 * M_PI * c->cfg.G, c->red_partial);
+    // 64 x 4 column tiles, z split so that the partials fit kRedBlocks slots
+    const int tx = (c->L.nx + 63) / 64, ty = (c->L.ny + 3) / 4;
+    const int cols = tx * ty;
+    int zsplit = std::max(1, std::min(c->L.nz, kRedBlocks / std::max(1, cols)));
+    int zc = (c->L.nz + zsplit - 1) / zsplit;
+    int nb = cols * ((c->L.nz + zc - 1) / zc);
+    if (nb > kRedBlocks) {  // very wide grids: one chunk per column tile is still too many
+        zc = c->L.nz;
+        nb = cols;
+    }
+    hipLaunchKernelGGL(k_residual_partial<S>, dim3(nb), dim3(64, 4), 0, c->stream, B<S>(c, c->cur),
+                       static_cast<const S*>(rho), c->L, idx2, 4.0 * M_PI * c->cfg.G, zc, tx, ty, c->red_partial);
     hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, c->stream, c->red_partial, nb, c->red_out);
 }
 
@@ -387,7 +429,9 @@ void run_raw_in(hgs_ctx* c, const void* a, const void* b) {
                        static_cast<const S*>(b), c->L, B<S>(c, c->old));
 }
 
-int default_tblock(const hgs_config* cfg) { return cfg->tblock > 0 ? cfg->tblock : 1; }
+// Default fused depth: four substeps per launch (the usual substeps per hydro
+// step); cfg->tblock or hgs_set_tblock override it.
+int default_tblock(const hgs_config* cfg) { return cfg->tblock > 0 ? cfg->tblock : 4; }
 
 }  // namespace
 
@@ -462,6 +506,7 @@ hgs_status hgs_init(const hgs_config* cfg, void* workspace, size_t bytes, hgs_ct
     c->mom_zc = p.mom_zc;
     c->mom_tx = p.mom_tx;
     c->mom_ty = p.mom_ty;
+    c->mom_vec = p.mom_vec;
     c->red_partial = reinterpret_cast<double*>(w + p.red_partial_off);
     c->red_out = reinterpret_cast<double*>(w + p.red_out_off);
     c->red_blocks = kRedBlocks;
@@ -470,6 +515,14 @@ hgs_status hgs_init(const hgs_config* cfg, void* workspace, size_t bytes, hgs_ct
     c->tblock = default_tblock(cfg);
     c->timing = false;
     c->pool_used = 0;
+    {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            c->ncu = n;
+        else
+            c->ncu = 256;
+    }
     (void)hipGetLastError();
     DISPATCH(c, run_init, c);
     s = launch_check(c, "hgs_init");
@@ -528,8 +581,8 @@ hgs_status hgs_timing_read(hgs_ctx* ctx, int32_t kind, double out[4]) {
 
 hgs_status hgs_set_tblock(hgs_ctx* ctx, int32_t tblock) {
     if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
-    if (tblock < 0 || tblock > HGS_TMAX) return fail(ctx, HGS_ERR_ARG, "tblock must be in 0..8");
-    ctx->tblock = tblock == 0 ? 1 : tblock;
+    if (tblock < 0 || tblock > HGS_TMAX) return fail(ctx, HGS_ERR_ARG, "tblock must be in 0..4");
+    ctx->tblock = tblock == 0 ? 4 : tblock;
     return HGS_OK;
 }
 

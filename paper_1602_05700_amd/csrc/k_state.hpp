@@ -150,39 +150,53 @@ __global__ void k_faces_in(const S* __restrict__ src, Layout L, S* b0, S* b1, S*
 // Residual partial sums per workgroup: [rr, bb, ss, pp, bad].
 //   r = L_h phi - s,  b = s - (adjacent ghosts)/dx^2,  s = 4 pi G rho.
 constexpr int NRED = 5;
+// One workgroup per (64 x 4 column tile, z chunk); each thread marches its
+// column.  Fixed-order reductions: wave butterfly, then the four waves.
 template <typename S>
 __global__ __launch_bounds__(256) void k_residual_partial(const S* __restrict__ phi, const S* __restrict__ rho,
-                                                          Layout L, double idx2, double four_pi_g,
-                                                          double* __restrict__ partial) {
+                                                          Layout L, double idx2, double four_pi_g, int zc,
+                                                          int tiles_x, int tiles_y, double* __restrict__ partial) {
     __shared__ double red[4][NRED];
     double acc[NRED] = {0, 0, 0, 0, 0};
-    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
-    HGS_GRID_STRIDE(t, n) {
-        Flat f = unflat(t, L);
-        const int64_t o = L.idx(f.i, f.j, f.k);
-        const double c = (double)phi[o];
-        const double xm = (double)phi[o - 1], xp = (double)phi[o + 1];
-        const double ym = (double)phi[o - L.pitch], yp = (double)phi[o + L.pitch];
-        const double zm = (double)phi[o - L.plane], zp = (double)phi[o + L.plane];
-        double gb = 0.0;
-        if (f.i == 0) gb += xm;
-        if (f.i == L.nx - 1) gb += xp;
-        if (f.j == 0) gb += ym;
-        if (f.j == L.ny - 1) gb += yp;
-        if (f.k == 0) gb += zm;
-        if (f.k == L.nz - 1) gb += zp;
-        const double rv = (double)rho[t];
-        const double s = four_pi_g * rv;
-        const double nb = ((xm + xp) + (ym + yp)) + (zm + zp);
-        const double r = (nb - 6.0 * c) * idx2 - s;
-        const double b = s - gb * idx2;
-        acc[0] += r * r;
-        acc[1] += b * b;
-        acc[2] += s * s;
-        acc[3] += c * c;
-        if (!isfinite(c) || !isfinite(rv)) acc[4] = 1.0;
+    const int bid = blockIdx.x;
+    const int tx = bid % tiles_x;
+    const int ty = (bid / tiles_x) % tiles_y;
+    const int tz = bid / (tiles_x * tiles_y);
+    const int i = tx * 64 + threadIdx.x;
+    const int j = ty * 4 + threadIdx.y;
+    if (i < L.nx && j < L.ny) {
+        const int k0 = tz * zc;
+        const int k1 = min(k0 + zc, L.nz);
+        const int64_t sxy = (int64_t)L.nx * L.ny;
+        const S* pc = phi + L.idx(i, j, k0);
+        const S* pr = rho + (int64_t)k0 * sxy + (int64_t)j * L.nx + i;
+        for (int k = k0; k < k1; ++k) {
+            const double c = (double)pc[0];
+            const double xm = (double)pc[-1], xp = (double)pc[1];
+            const double ym = (double)pc[-L.pitch], yp = (double)pc[L.pitch];
+            const double zm = (double)pc[-L.plane], zp = (double)pc[L.plane];
+            double gb = 0.0;
+            if (i == 0) gb += xm;
+            if (i == L.nx - 1) gb += xp;
+            if (j == 0) gb += ym;
+            if (j == L.ny - 1) gb += yp;
+            if (k == 0) gb += zm;
+            if (k == L.nz - 1) gb += zp;
+            const double rv = (double)pr[0];
+            const double s = four_pi_g * rv;
+            const double nb = ((xm + xp) + (ym + yp)) + (zm + zp);
+            const double r = (nb - 6.0 * c) * idx2 - s;
+            const double b = s - gb * idx2;
+            acc[0] += r * r;
+            acc[1] += b * b;
+            acc[2] += s * s;
+            acc[3] += c * c;
+            if (!isfinite(c) || !isfinite(rv)) acc[4] = 1.0;
+            pc += L.plane;
+            pr += sxy;
+        }
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x, wave = threadIdx.y;
 #pragma unroll
     for (int q = 0; q < NRED; ++q) {
         double v = acc[q];
@@ -195,11 +209,11 @@ __global__ __launch_bounds__(256) void k_residual_partial(const S* __restrict__ 
         if (lane == 0) red[wave][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < NRED) {
-        const int q = threadIdx.x;
-        double v = (q == 4) ? fmax(fmax(red[0][q], red[1][q]), fmax(red[2][q], red[3][q]))
-                            : ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q]));
-        partial[(size_t)blockIdx.x * NRED + q] = v;
+    const int t = threadIdx.y * 64 + threadIdx.x;
+    if (t < NRED) {
+        double v = (t == 4) ? fmax(fmax(red[0][t], red[1][t]), fmax(red[2][t], red[3][t]))
+                            : ((red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
+        partial[(size_t)blockIdx.x * NRED + t] = v;
     }
 }
 

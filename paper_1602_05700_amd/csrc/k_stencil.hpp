@@ -91,3 +91,186 @@ __global__ __launch_bounds__(BX* BY) void k_gradient(const S* __restrict__ phi, 
 }
 
 }  // namespace hgs
+
+// ---------------------------------------------------------------------------
+// Vectorised forms (16 bytes per lane: 4 FP32 or 2 FP64 cells along x), used
+// when nx is a multiple of the vector width.  A wave covers 64*N consecutive x
+// cells of one row; x neighbours across lanes come from a DPP wave shift, and
+// only the first and last lane of a wave read their outer neighbour from
+// memory.  The arithmetic and its order are those of the scalar kernels, so
+// results are bit-identical.
+namespace hgs {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename S>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using T = f32x4;
+    static constexpr int N = 4;
+    __device__ static float get(const T& v, int i) { return v[i]; }
+    __device__ static void set(T& v, int i, float s) { v[i] = s; }
+};
+template <>
+struct Vec16<double> {
+    using T = f64x2;
+    static constexpr int N = 2;
+    __device__ static double get(const T& v, int i) { return v[i]; }
+    __device__ static void set(T& v, int i, double s) { v[i] = s; }
+};
+
+// value of lane l-1 (from_prev) or l+1 (from_next); edge lanes get 0
+__device__ __forceinline__ float from_prev(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_next(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double from_prev(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_next(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Per-lane geometry of a vectorised sweep: lanes past the interior load a
+// clamped (valid) vector and store nothing.
+struct VLane {
+    int i0;      // first x cell of the lane
+    int j;       // row
+    int xl, jl;  // clamped load coordinates (padded layout)
+    int xr, jr;  // clamped coordinates in a compact array
+    bool active;
+};
+
+template <int N>
+__device__ __forceinline__ VLane vlane(const Layout& L, int tx, int ty, int BY) {
+    VLane v;
+    const int lane = threadIdx.x;
+    v.i0 = (tx * 64 + lane) * N;
+    v.j = ty * BY + (int)threadIdx.y;
+    v.active = v.i0 < L.nx && v.j < L.ny;
+    v.xl = min(v.i0, L.nx);  // [nx, nx+N) lies inside the row padding
+    v.jl = min(v.j, L.ny);
+    v.xr = min(v.i0, L.nx - N);
+    v.jr = min(v.j, L.ny - 1);
+    return v;
+}
+
+template <typename S, int BY>
+__global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restrict__ cur, S* __restrict__ old_new,
+                                                               const S* __restrict__ rho, Layout L, StepCoef c, int zc,
+                                                               int tiles_x, int tiles_y) {
+    using V = Vec16<S>;
+    using VT = typename V::T;
+    constexpr int N = V::N;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = bid % tiles_x;
+    const int ty = (bid / tiles_x) % tiles_y;
+    const int tz = bid / (tiles_x * tiles_y);
+    const VLane g = vlane<N>(L, tx, ty, BY);
+    const int lane = threadIdx.x;
+    const int k0 = tz * zc;
+    const int k1 = min(k0 + zc, L.nz);
+    const int64_t plane = L.plane;
+    const int pitch = L.pitch;
+    const int64_t o0 = L.idx(g.xl, g.jl, k0);
+    const S* pc = cur + o0;
+    S* po = old_new + o0;
+    const int64_t sxy = (int64_t)L.nx * L.ny;
+    const S* pr = rho + (int64_t)k0 * sxy + (int64_t)g.jr * L.nx + g.xr;
+    VT zm = *reinterpret_cast<const VT*>(pc - plane);
+    VT z0 = *reinterpret_cast<const VT*>(pc);
+    for (int k = k0; k < k1; ++k) {
+        const VT zp = *reinterpret_cast<const VT*>(pc + plane);
+        const VT ym = *reinterpret_cast<const VT*>(pc - pitch);
+        const VT yp = *reinterpret_cast<const VT*>(pc + pitch);
+        const VT o = *reinterpret_cast<const VT*>(po);
+        const VT r = *reinterpret_cast<const VT*>(pr);
+        S left = from_prev(V::get(z0, N - 1));
+        S right = from_next(V::get(z0, 0));
+        if (lane == 0) left = pc[-1];
+        if (lane == 63) right = pc[N];
+        VT out;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const double xm = n > 0 ? (double)V::get(z0, n - 1) : (double)left;
+            const double xp = n < N - 1 ? (double)V::get(z0, n + 1) : (double)right;
+            const double v = leapfrog_update(c, (double)V::get(z0, n), xm, xp, (double)V::get(ym, n),
+                                             (double)V::get(yp, n), (double)V::get(zm, n), (double)V::get(zp, n),
+                                             (double)V::get(o, n), (double)V::get(r, n));
+            V::set(out, n, (S)v);
+        }
+        if (g.active) *reinterpret_cast<VT*>(po) = out;
+        zm = z0;
+        z0 = zp;
+        pc += plane;
+        po += plane;
+        pr += sxy;
+    }
+}
+
+template <typename S, int BY>
+__global__ __launch_bounds__(64 * BY) void k_gradient_v(const S* __restrict__ phi, Layout L, double half_inv_dx,
+                                                        int zc, int tiles_x, int tiles_y, S* __restrict__ gx,
+                                                        S* __restrict__ gy, S* __restrict__ gz) {
+    using V = Vec16<S>;
+    using VT = typename V::T;
+    constexpr int N = V::N;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = bid % tiles_x;
+    const int ty = (bid / tiles_x) % tiles_y;
+    const int tz = bid / (tiles_x * tiles_y);
+    const VLane g = vlane<N>(L, tx, ty, BY);
+    const int lane = threadIdx.x;
+    const int k0 = tz * zc;
+    const int k1 = min(k0 + zc, L.nz);
+    const int64_t plane = L.plane;
+    const int pitch = L.pitch;
+    const S* pc = phi + L.idx(g.xl, g.jl, k0);
+    const int64_t sxy = (int64_t)L.nx * L.ny;
+    const int64_t c0 = (int64_t)k0 * sxy + (int64_t)g.jr * L.nx + g.xr;
+    VT* ox = reinterpret_cast<VT*>(gx + c0);
+    VT* oy = reinterpret_cast<VT*>(gy + c0);
+    VT* oz = reinterpret_cast<VT*>(gz + c0);
+    const int64_t vsxy = sxy / N;
+    VT zm = *reinterpret_cast<const VT*>(pc - plane);
+    VT z0 = *reinterpret_cast<const VT*>(pc);
+    for (int k = k0; k < k1; ++k) {
+        const VT zp = *reinterpret_cast<const VT*>(pc + plane);
+        const VT ym = *reinterpret_cast<const VT*>(pc - pitch);
+        const VT yp = *reinterpret_cast<const VT*>(pc + pitch);
+        S left = from_prev(V::get(z0, N - 1));
+        S right = from_next(V::get(z0, 0));
+        if (lane == 0) left = pc[-1];
+        if (lane == 63) right = pc[N];
+        VT ax, ay, az;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const double xm = n > 0 ? (double)V::get(z0, n - 1) : (double)left;
+            const double xp = n < N - 1 ? (double)V::get(z0, n + 1) : (double)right;
+            V::set(ax, n, (S)(-(xp - xm) * half_inv_dx));
+            V::set(ay, n, (S)(-((double)V::get(yp, n) - (double)V::get(ym, n)) * half_inv_dx));
+            V::set(az, n, (S)(-((double)V::get(zp, n) - (double)V::get(zm, n)) * half_inv_dx));
+        }
+        if (g.active) {
+            __builtin_nontemporal_store(ax, ox);
+            __builtin_nontemporal_store(ay, oy);
+            __builtin_nontemporal_store(az, oz);
+        }
+        zm = z0;
+        z0 = zp;
+        pc += plane;
+        ox += vsxy;
+        oy += vsxy;
+        oz += vsxy;
+    }
+}
+
+}  // namespace hgs

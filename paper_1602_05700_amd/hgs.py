@@ -32,7 +32,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 HGS_OK, HGS_ERR_ARG, HGS_ERR_CFL, HGS_ERR_WORKSPACE, HGS_ERR_DEVICE, HGS_ERR_NONFINITE, HGS_ERR_STATE = range(7)
 HGS_F64, HGS_F32 = 0, 1
 HGS_BC_MULTIPOLE, HGS_BC_USER = 0, 1
-TMAX = 8
+TMAX = 4
 LMAX = 4
 
 

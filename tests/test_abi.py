@@ -48,7 +48,7 @@ def test_config_cube_defaults():
 
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("ny", -3), ("nz", 9000), ("dx", 0.0), ("dx", float("nan")), ("lmax", 5), ("lmax", -1),
-    ("bc", 2), ("storage", 7), ("tblock", 9), ("tblock", -1), ("eta", -0.5), ("eta", float("inf")),
+    ("bc", 2), ("storage", 7), ("tblock", 5), ("tblock", -1), ("eta", -0.5), ("eta", float("inf")),
     ("G", float("nan")),
 ])
 def test_bad_config_rejected(field, value):

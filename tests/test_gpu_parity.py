@@ -356,3 +356,41 @@ def test_full_size_512_f32_two_hydro_steps(gpu_lib):
     assert rel(host(pd), rpd) < 10 * F32_TOL
     for a, b in zip((gx, gy, gz), o.accel()):
         assert rel(host(a), b) < 10 * F32_TOL
+
+
+# ------------------------------------------------------------------ temporal blocking
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 3, 7), (23, 29, 37), (40, 33, 130), (70, 61, 66)])
+@pytest.mark.parametrize("T", [2, 3, 4])
+def test_tblock_bitwise_equals_streaming(gpu_lib, storage, shape, T):
+    """Fused launches of T substeps give exactly the streaming results: every
+    level is rounded like a streamed store and ghosts stay frozen.  nsub values
+    that are not multiples of T and a dt change are included."""
+    import torch
+
+    g = grid_of(shape)
+    rho = to_dev(dens(shape, 12, storage))
+    a = solver(gpu_lib, shape, storage=storage, eta=0.7, tblock=1)
+    b = solver(gpu_lib, shape, storage=storage, eta=0.7, tblock=T)
+    assert a.tblock == 1 and b.tblock == T
+    for dt, nsub in [(0.4, T), (0.4, 2 * T + 1), (0.3, 5), (0.45, 3 * T)]:
+        a.step(rho, 1.0, dt * g.dx, nsub)
+        b.step(rho, 1.0, dt * g.dx, nsub)
+    ra, rb = a.save_raw(), b.save_raw()
+    torch.cuda.synchronize()
+    assert torch.equal(ra[0], rb[0]) and torch.equal(ra[1], rb[1])
+    ga, gb = a.accel(), b.accel()
+    assert all(torch.equal(u, v) for u, v in zip(ga, gb))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_tblock_against_oracle(gpu_lib, storage):
+    shape = (48, 52, 70)
+    g = grid_of(shape)
+    rho = dens(shape, 13, storage)
+    s, o = pair(gpu_lib, shape, storage, eta=0.0, tblock=4)
+    for _ in range(5):
+        s.step(to_dev(rho), 1.0, 0.4 * g.dx, 4)
+        o.step(rho.astype(np.float64), 1.0, 0.4 * g.dx, 4)
+    compare_state(s, o, storage, F64_TOL if storage == "f64" else F32_TOL)
