@@ -90,7 +90,20 @@ def main():
     ap.add_argument("--nsub", type=int, default=4)
     ap.add_argument("--tblock", type=int, default=0, help="substeps per fused launch (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy five times (for scaling HBM counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 5}), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
