@@ -179,6 +179,32 @@ typedef enum { HGS_KERNEL_STENCIL = 0, HGS_KERNEL_MULTIPOLE = 1, HGS_KERNEL_GRAD
 hgs_status hgs_timing_enable(hgs_ctx* ctx, int32_t enable);
 hgs_status hgs_timing_read(hgs_ctx* ctx, int32_t kind, double out[4]);
 
+/* ---- Batched form: many independent grids stepped together ------------------
+ * A batch is n ordinary contexts carved from one workspace; hgs_batch_grid
+ * gives grid i's context for every single-grid call (potential, accel,
+ * residual, set_state, ...).  hgs_step_batch performs one hydrodynamical step
+ * on all grids: per grid the multipole moments and ghosts, then nsub substeps
+ * for every grid in launches that each cover all grids (a persistent work list
+ * of tiles sorted by cost), replayed from a captured hipGraph of the substep
+ * sequence.  Results are bit-identical to stepping each grid alone with the
+ * same tblock.  Requirements: all grids share storage, stream and tblock (taken
+ * from cfgs[0]); every nx is a multiple of the 16-byte vector width (4 for
+ * FP32, 2 for FP64). */
+typedef struct hgs_batch hgs_batch;
+hgs_status hgs_workspace_bytes_batch(const hgs_config* cfgs, int32_t n, size_t* bytes);
+hgs_status hgs_init_batch(const hgs_config* cfgs, int32_t n, void* workspace, size_t bytes, hgs_batch** out);
+/* Grid i's context, owned by the batch (do not destroy it). */
+hgs_status hgs_batch_grid(hgs_batch* b, int32_t i, hgs_ctx** ctx);
+/* rho: host array of n device pointers; c_g, dt: host arrays of n values.
+ * Validates every grid (as hgs_step) before enqueueing anything. */
+hgs_status hgs_step_batch(hgs_batch* b, const void* const* rho, const double* c_g, const double* dt, int32_t nsub);
+/* Whether the last hgs_step_batch replayed a captured graph (1) or fell back
+ * to direct launches (0). */
+int32_t hgs_batch_used_graph(const hgs_batch* b);
+/* Reason for the batch's last non-OK status ("" if none). */
+const char* hgs_batch_last_error(const hgs_batch* b);
+hgs_status hgs_destroy_batch(hgs_batch* b);
+
 /* Release the host context (the workspace stays the caller's).  NULL is a no-op. */
 hgs_status hgs_destroy(hgs_ctx* ctx);
 

@@ -20,6 +20,10 @@
 #include "k_state.hpp"
 #include "k_stencil.hpp"
 #include "k_tblock.hpp"
+#include "k_batch.hpp"
+#include <algorithm>
+#include <map>
+#include <tuple>
 
 using namespace hgs;
 
@@ -737,6 +741,405 @@ hgs_status hgs_load_raw(hgs_ctx* ctx, const void* phi_n, const void* phi_nm1, do
     DISPATCH(ctx, run_raw_in, ctx, phi_n, phi_nm1);
     ctx->dt_prev = dt_prev;
     return launch_check(ctx, "hgs_load_raw");
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batched form
+// ============================================================================
+
+struct hgs_batch {
+    int n;
+    hgs_dtype storage;
+    int tblock;
+    hipStream_t stream;
+    std::vector<hgs_ctx*> grids;
+    void* desc_dev;     // GridDesc<S>[n]
+    WorkItem* tb_items;
+    int n_tb_items;
+    WorkItem* st_items;
+    int n_st_items;
+    // host staging of the descriptors, double-buffered: buffer k is refilled
+    // only after the event recorded behind its previous upload has passed
+    std::vector<unsigned char> desc_host[2];
+    hipEvent_t desc_done[2];
+    bool desc_pending[2];
+    int desc_k;
+    hipStream_t capture;  // stream used only to record graphs
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (nsub, T, cur, old)
+    bool graph_ok;
+    bool used_graph;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_err;
+
+hgs_status bfail(hgs_batch* b, hgs_status s, const std::string& m) {
+    if (b)
+        b->err = m;
+    else
+        g_err = m;
+    return s;
+}
+
+struct BatchPlan {
+    std::vector<size_t> grid_off, grid_bytes;
+    size_t desc_off, tb_off, st_off, total;
+    std::vector<WorkItem> tb_items, st_items;
+};
+
+template <typename S>
+void batch_items(const std::vector<Layout>& Ls, int T, std::vector<WorkItem>& tb, std::vector<WorkItem>& st) {
+    tb.clear();
+    st.clear();
+    std::vector<std::pair<int64_t, WorkItem>> a, b;
+    for (int g = 0; g < (int)Ls.size(); ++g) {
+        const Layout& L = Ls[g];
+        if (T > 1) {
+            int IX = 64 - 2 * T, IY = 0;
+            switch (T) {
+                case 2: IY = TBConfig<S, 2>::W * TBConfig<S, 2>::R - 4; break;
+                case 3: IY = TBConfig<S, 3>::W * TBConfig<S, 3>::R - 6; break;
+                default: IY = TBConfig<S, 4>::W * TBConfig<S, 4>::R - 8; break;
+            }
+            const int tx = (L.nx + IX - 1) / IX, ty = (L.ny + IY - 1) / IY;
+            const int zc = std::min(L.nz, 64);
+            for (int z = 0; z < L.nz; z += zc)
+                for (int y = 0; y < ty; ++y)
+                    for (int x = 0; x < tx; ++x) {
+                        WorkItem w{g, x, y, z, std::min(L.nz, z + zc)};
+                        a.push_back({(int64_t)(w.k1 - w.k0 + 2 * T), w});
+                    }
+        }
+        const int N = 16 / (int)sizeof(S);
+        const int tx = (L.nx + 64 * N - 1) / (64 * N), ty = (L.ny + 3) / 4;
+        const int zc = std::min(L.nz, 32);
+        for (int z = 0; z < L.nz; z += zc)
+            for (int y = 0; y < ty; ++y)
+                for (int x = 0; x < tx; ++x) {
+                    WorkItem w{g, x, y, z, std::min(L.nz, z + zc)};
+                    const int wx = std::min(64 * N, L.nx - x * 64 * N);
+                    b.push_back({(int64_t)wx * (w.k1 - w.k0), w});
+                }
+    }
+    auto by_cost = [](const std::pair<int64_t, WorkItem>& p, const std::pair<int64_t, WorkItem>& q) {
+        return p.first > q.first;
+    };
+    std::stable_sort(a.begin(), a.end(), by_cost);
+    std::stable_sort(b.begin(), b.end(), by_cost);
+    for (auto& p : a) tb.push_back(p.second);
+    for (auto& p : b) st.push_back(p.second);
+}
+
+hgs_status batch_plan(const hgs_config* cfgs, int32_t n, BatchPlan& p, std::string& why) {
+    if (!cfgs || n < 1 || n > 4096) {
+        why = "need 1 <= n <= 4096 configurations";
+        return HGS_ERR_ARG;
+    }
+    std::vector<Layout> Ls;
+    for (int i = 0; i < n; ++i) {
+        hgs_status s = check_config(&cfgs[i], why);
+        if (s != HGS_OK) {
+            why = "grid " + std::to_string(i) + ": " + why;
+            return s;
+        }
+        if (cfgs[i].storage != cfgs[0].storage || cfgs[i].stream != cfgs[0].stream ||
+            cfgs[i].tblock != cfgs[0].tblock) {
+            why = "all grids of a batch share storage, stream and tblock";
+            return HGS_ERR_ARG;
+        }
+        const int vec = cfgs[i].storage == HGS_F64 ? 2 : 4;
+        if (cfgs[i].nx % vec) {
+            why = "grid " + std::to_string(i) + ": nx must be a multiple of " + std::to_string(vec) + " in a batch";
+            return HGS_ERR_ARG;
+        }
+        Ls.push_back(make_layout(cfgs[i].nx, cfgs[i].ny, cfgs[i].nz, cfgs[i].storage == HGS_F64 ? 8 : 4));
+    }
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        size_t b = make_plan(&cfgs[i]).total;
+        p.grid_off.push_back(off);
+        p.grid_bytes.push_back(b);
+        off = align_up(off + b, kAlign);
+    }
+    const int T = default_tblock(&cfgs[0]);
+    if (cfgs[0].storage == HGS_F64)
+        batch_items<double>(Ls, T, p.tb_items, p.st_items);
+    else
+        batch_items<float>(Ls, T, p.tb_items, p.st_items);
+    const size_t dsz = cfgs[0].storage == HGS_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
+    p.desc_off = off;
+    off = align_up(off + dsz * n, kAlign);
+    p.tb_off = off;
+    off = align_up(off + sizeof(WorkItem) * std::max<size_t>(1, p.tb_items.size()), kAlign);
+    p.st_off = off;
+    off = align_up(off + sizeof(WorkItem) * std::max<size_t>(1, p.st_items.size()), kAlign);
+    p.total = off;
+    return HGS_OK;
+}
+
+template <typename S>
+void batch_fill_desc(hgs_batch* b, std::vector<unsigned char>& host, const void* const* rho, const double* c_g,
+                     const double* dt) {
+    host.resize(sizeof(GridDesc<S>) * b->n);
+    GridDesc<S>* d = reinterpret_cast<GridDesc<S>*>(host.data());
+    for (int i = 0; i < b->n; ++i) {
+        hgs_ctx* c = b->grids[i];
+        d[i].L = c->L;
+        d[i].c = step_coef(c, c_g[i], dt[i]);
+        for (int k = 0; k < 4; ++k) d[i].buf[k] = static_cast<S*>(c->buf[k]);
+        d[i].rho = static_cast<const S*>(rho[i]);
+    }
+}
+
+// The launches of nsub substeps for all grids, starting from buffers (cur, old).
+template <typename S>
+void batch_launches(hgs_batch* b, int nsub, int cur, int old, hipStream_t st) {
+    const GridDesc<S>* d = static_cast<const GridDesc<S>*>(b->desc_dev);
+    const int ncu = b->grids[0]->ncu;
+    const int T = b->tblock;
+    while (nsub > 0) {
+        if (T > 1 && nsub >= T) {
+            int o0 = -1, o1 = -1;
+            for (int k = 0; k < 4; ++k)
+                if (k != cur && k != old) {
+                    if (o0 < 0)
+                        o0 = k;
+                    else
+                        o1 = k;
+                }
+            const int nb = std::min(b->n_tb_items, ncu);
+            switch (T) {
+                case 2:
+                    hipLaunchKernelGGL((k_tblock_batch<S, 2, TBConfig<S, 2>::R, TBConfig<S, 2>::W>), dim3(nb),
+                                       dim3(64 * TBConfig<S, 2>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
+                                       o0, o1);
+                    break;
+                case 3:
+                    hipLaunchKernelGGL((k_tblock_batch<S, 3, TBConfig<S, 3>::R, TBConfig<S, 3>::W>), dim3(nb),
+                                       dim3(64 * TBConfig<S, 3>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
+                                       o0, o1);
+                    break;
+                default:
+                    hipLaunchKernelGGL((k_tblock_batch<S, 4, TBConfig<S, 4>::R, TBConfig<S, 4>::W>), dim3(nb),
+                                       dim3(64 * TBConfig<S, 4>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
+                                       o0, o1);
+                    break;
+            }
+            cur = o0;
+            old = o1;
+            nsub -= T;
+        } else {
+            const int nb = std::min(b->n_st_items, ncu * 8);
+            hipLaunchKernelGGL((k_stream_batch<S, SBY>), dim3(nb), dim3(64, SBY), 0, st, d, b->st_items,
+                               b->n_st_items, cur, old);
+            std::swap(cur, old);
+            nsub -= 1;
+        }
+    }
+}
+
+// buffer roles after nsub substeps from (cur, old)
+void batch_roles(int T, int nsub, int& cur, int& old) {
+    while (nsub > 0) {
+        if (T > 1 && nsub >= T) {
+            int o0 = -1, o1 = -1;
+            for (int k = 0; k < 4; ++k)
+                if (k != cur && k != old) {
+                    if (o0 < 0)
+                        o0 = k;
+                    else
+                        o1 = k;
+                }
+            cur = o0;
+            old = o1;
+            nsub -= T;
+        } else {
+            std::swap(cur, old);
+            nsub -= 1;
+        }
+    }
+}
+
+template <typename S>
+hgs_status batch_run(hgs_batch* b, int nsub) {
+    const int cur = b->grids[0]->cur, old = b->grids[0]->old;
+    b->used_graph = false;
+    if (b->graph_ok) {
+        auto key = std::make_tuple(nsub, b->tblock, cur, old);
+        auto it = b->graphs.find(key);
+        hipGraphExec_t exec = nullptr;
+        if (it != b->graphs.end()) {
+            exec = it->second;
+        } else {
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                batch_launches<S>(b, nsub, cur, old, b->capture);
+                ok = hipStreamEndCapture(b->capture, &graph) == hipSuccess && graph;
+            }
+            if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (ok) {
+                b->graphs[key] = exec;
+            } else {
+                exec = nullptr;
+                b->graph_ok = false;  // capture unsupported here: launch directly from now on
+            }
+        }
+        if (exec) {
+            if (hipGraphLaunch(exec, b->stream) != hipSuccess) return bfail(b, HGS_ERR_DEVICE, "hipGraphLaunch failed");
+            b->used_graph = true;
+        }
+    }
+    if (!b->used_graph) batch_launches<S>(b, nsub, cur, old, b->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, HGS_ERR_DEVICE, std::string("hgs_step_batch: ") + hipGetErrorString(e));
+    int c2 = cur, o2 = old;
+    batch_roles(b->tblock, nsub, c2, o2);
+    for (hgs_ctx* c : b->grids) {
+        c->cur = c2;
+        c->old = o2;
+    }
+    return HGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hgs_status hgs_workspace_bytes_batch(const hgs_config* cfgs, int32_t n, size_t* bytes) {
+    if (!bytes) return fail(nullptr, HGS_ERR_ARG, "bytes is NULL");
+    BatchPlan p;
+    std::string why;
+    hgs_status s = batch_plan(cfgs, n, p, why);
+    if (s != HGS_OK) return fail(nullptr, s, why);
+    *bytes = p.total;
+    return HGS_OK;
+}
+
+hgs_status hgs_init_batch(const hgs_config* cfgs, int32_t n, void* workspace, size_t bytes, hgs_batch** out) {
+    if (!out) return fail(nullptr, HGS_ERR_ARG, "out is NULL");
+    BatchPlan p;
+    std::string why;
+    hgs_status s = batch_plan(cfgs, n, p, why);
+    if (s != HGS_OK) return fail(nullptr, s, why);
+    if (!workspace) return fail(nullptr, HGS_ERR_WORKSPACE, "workspace is NULL");
+    if (bytes < p.total) return fail(nullptr, HGS_ERR_WORKSPACE, "workspace smaller than hgs_workspace_bytes_batch()");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(nullptr, HGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    hgs_batch* b = new (std::nothrow) hgs_batch();
+    if (!b) return fail(nullptr, HGS_ERR_ARG, "out of host memory");
+    char* w = static_cast<char*>(workspace);
+    b->n = n;
+    b->storage = (hgs_dtype)cfgs[0].storage;
+    b->tblock = default_tblock(&cfgs[0]);
+    b->stream = static_cast<hipStream_t>(cfgs[0].stream);
+    b->graph_ok = true;
+    b->used_graph = false;
+    b->capture = nullptr;
+    b->desc_k = 0;
+    b->desc_pending[0] = b->desc_pending[1] = false;
+    b->desc_done[0] = b->desc_done[1] = nullptr;
+    for (int i = 0; i < n; ++i) {
+        hgs_ctx* c = nullptr;
+        s = hgs_init(&cfgs[i], w + p.grid_off[i], p.grid_bytes[i], &c);
+        if (s != HGS_OK) {
+            for (hgs_ctx* q : b->grids) hgs_destroy(q);
+            delete b;
+            return s;
+        }
+        b->grids.push_back(c);
+    }
+    b->desc_dev = w + p.desc_off;
+    b->tb_items = reinterpret_cast<WorkItem*>(w + p.tb_off);
+    b->st_items = reinterpret_cast<WorkItem*>(w + p.st_off);
+    b->n_tb_items = (int)p.tb_items.size();
+    b->n_st_items = (int)p.st_items.size();
+    hipError_t e = hipSuccess;
+    if (!p.tb_items.empty())
+        e = hipMemcpyAsync(b->tb_items, p.tb_items.data(), sizeof(WorkItem) * p.tb_items.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->st_items, p.st_items.data(), sizeof(WorkItem) * p.st_items.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->desc_done[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->desc_done[1], hipEventDisableTiming);
+    if (e == hipSuccess && hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+        b->capture = nullptr;
+        b->graph_ok = false;
+    }
+    if (e != hipSuccess) {
+        for (hgs_ctx* q : b->grids) hgs_destroy(q);
+        delete b;
+        return fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_init_batch: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return HGS_OK;
+}
+
+hgs_status hgs_batch_grid(hgs_batch* b, int32_t i, hgs_ctx** ctx) {
+    if (!b || !ctx) return fail(nullptr, HGS_ERR_ARG, "batch and ctx must be non-NULL");
+    if (i < 0 || i >= b->n) return bfail(b, HGS_ERR_ARG, "grid index out of range");
+    *ctx = b->grids[i];
+    return HGS_OK;
+}
+
+int32_t hgs_batch_used_graph(const hgs_batch* b) { return b && b->used_graph ? 1 : 0; }
+
+const char* hgs_batch_last_error(const hgs_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+hgs_status hgs_step_batch(hgs_batch* b, const void* const* rho, const double* c_g, const double* dt, int32_t nsub) {
+    if (!b) return fail(nullptr, HGS_ERR_ARG, "batch is NULL");
+    if (!rho || !c_g || !dt) return bfail(b, HGS_ERR_ARG, "rho, c_g and dt must be non-NULL");
+    for (int i = 0; i < b->n; ++i) {
+        hgs_status s = validate_step(b->grids[i], &b->grids[i]->cfg, rho[i], c_g[i], dt[i], nsub);
+        if (s != HGS_OK) return bfail(b, s, "grid " + std::to_string(i) + ": " + b->grids[i]->err);
+    }
+    (void)hipGetLastError();
+    for (int i = 0; i < b->n; ++i) {
+        hgs_ctx* c = b->grids[i];
+        if (c->cfg.bc == HGS_BC_MULTIPOLE) {
+            DISPATCH(c, run_moments_and_ghosts, c, rho[i]);
+            c->have_moments = true;
+        }
+        if (c->dt_prev > 0.0 && dt[i] != c->dt_prev) DISPATCH(c, run_rescale, c, dt[i] / c->dt_prev);
+    }
+    const int k = b->desc_k;
+    b->desc_k ^= 1;
+    hipError_t e = hipSuccess;
+    if (b->desc_pending[k]) e = hipEventSynchronize(b->desc_done[k]);
+    if (e != hipSuccess) return bfail(b, HGS_ERR_DEVICE, std::string("descriptor staging: ") + hipGetErrorString(e));
+    if (b->storage == HGS_F64)
+        batch_fill_desc<double>(b, b->desc_host[k], rho, c_g, dt);
+    else
+        batch_fill_desc<float>(b, b->desc_host[k], rho, c_g, dt);
+    e = hipMemcpyAsync(b->desc_dev, b->desc_host[k].data(), b->desc_host[k].size(), hipMemcpyHostToDevice,
+                       b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->desc_done[k], b->stream);
+    if (e != hipSuccess) return bfail(b, HGS_ERR_DEVICE, std::string("descriptor upload: ") + hipGetErrorString(e));
+    b->desc_pending[k] = true;
+    hgs_status s = b->storage == HGS_F64 ? batch_run<double>(b, nsub) : batch_run<float>(b, nsub);
+    if (s != HGS_OK) return s;
+    for (int i = 0; i < b->n; ++i) b->grids[i]->dt_prev = dt[i];
+    return HGS_OK;
+}
+
+hgs_status hgs_destroy_batch(hgs_batch* b) {
+    if (!b) return HGS_OK;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (int k = 0; k < 2; ++k)
+        if (b->desc_done[k]) (void)hipEventDestroy(b->desc_done[k]);
+    for (hgs_ctx* c : b->grids) hgs_destroy(c);
+    delete b;
+    return HGS_OK;
 }
 
 }  // extern "C"

@@ -163,21 +163,17 @@ __device__ __forceinline__ VLane vlane(const Layout& L, int tx, int ty, int BY) 
     return v;
 }
 
+// One (64N x BY) column tile, planes [k0, k1): the body shared by the
+// single-grid and the batched launches.
 template <typename S, int BY>
-__global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restrict__ cur, S* __restrict__ old_new,
-                                                               const S* __restrict__ rho, Layout L, StepCoef c, int zc,
-                                                               int tiles_x, int tiles_y) {
+__device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __restrict__ old_new,
+                                              const S* __restrict__ rho, const Layout& L, const StepCoef& c, int tx,
+                                              int ty, int k0, int k1) {
     using V = Vec16<S>;
     using VT = typename V::T;
     constexpr int N = V::N;
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = bid % tiles_x;
-    const int ty = (bid / tiles_x) % tiles_y;
-    const int tz = bid / (tiles_x * tiles_y);
     const VLane g = vlane<N>(L, tx, ty, BY);
     const int lane = threadIdx.x;
-    const int k0 = tz * zc;
-    const int k1 = min(k0 + zc, L.nz);
     const int64_t plane = L.plane;
     const int pitch = L.pitch;
     const int64_t o0 = L.idx(g.xl, g.jl, k0);
@@ -214,6 +210,18 @@ __global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restri
         po += plane;
         pr += sxy;
     }
+}
+
+template <typename S, int BY>
+__global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restrict__ cur, S* __restrict__ old_new,
+                                                               const S* __restrict__ rho, Layout L, StepCoef c, int zc,
+                                                               int tiles_x, int tiles_y) {
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = bid % tiles_x;
+    const int ty = (bid / tiles_x) % tiles_y;
+    const int tz = bid / (tiles_x * tiles_y);
+    const int k0 = tz * zc;
+    stream_v_tile<S, BY>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz));
 }
 
 template <typename S, int BY>

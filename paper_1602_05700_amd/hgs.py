@@ -69,6 +69,13 @@ _SIGS = {
     "hgs_get_tblock": (_i32, [_vp]),
     "hgs_timing_enable": (_i32, [_vp, _i32]),
     "hgs_timing_read": (_i32, [_vp, _i32, _dp]),
+    "hgs_workspace_bytes_batch": (_i32, [_CFG, _i32, ctypes.POINTER(_sz)]),
+    "hgs_init_batch": (_i32, [_CFG, _i32, _vp, _sz, ctypes.POINTER(_vp)]),
+    "hgs_batch_grid": (_i32, [_vp, _i32, ctypes.POINTER(_vp)]),
+    "hgs_step_batch": (_i32, [_vp, ctypes.POINTER(_vp), _dp, _dp, _i32]),
+    "hgs_batch_used_graph": (_i32, [_vp]),
+    "hgs_batch_last_error": (_cp, [_vp]),
+    "hgs_destroy_batch": (_i32, [_vp]),
     "hgs_destroy": (_i32, [_vp]),
     "hgs_status_str": (_cp, [_i32]),
     "hgs_last_error": (_cp, [_vp]),
@@ -148,6 +155,25 @@ class Solver:
         h = _vp()
         _check(_lib.hgs_init(ctypes.byref(self.cfg), self.workspace.data_ptr(), nbytes, ctypes.byref(h)))
         self._h = h
+        self._owned = True
+
+    @classmethod
+    def _view(cls, handle, cfg, device, dtype, stream, owner):
+        """A Solver over a context owned by a Batch (not destroyed by close())."""
+        import torch
+
+        obj = cls.__new__(cls)
+        obj.torch = torch
+        obj.device = device
+        obj.dtype = dtype
+        obj.stream = stream
+        obj.cfg = cfg
+        obj.shape = (cfg.nz, cfg.ny, cfg.nx)
+        obj.workspace = None
+        obj._h = handle
+        obj._owned = False
+        obj._owner = owner  # keeps the batch (and its workspace) alive
+        return obj
 
     # -- helpers
     def _need(self, t, shape=None):
@@ -250,8 +276,73 @@ class Solver:
         return int(_lib.hgs_get_tblock(self._h))
 
     def close(self) -> None:
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owned", True):
             _lib.hgs_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent cube or box grids stepped together (one launch per fused
+    substep group covering all grids, replayed from a captured hipGraph)."""
+
+    def __init__(self, shapes, dxs=None, x0s=None, G: float = 1.0, lmax: int = 4, storage: str = "f32",
+                 tblock: int = 0, eta=0.0, device="cuda", stream=None):
+        import torch
+
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.dtype = torch.float32 if storage == "f32" else torch.float64
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        n = len(shapes)
+        self.n = n
+        etas = list(eta) if not np.isscalar(eta) else [eta] * n
+        self.cfgs = (Config * n)()
+        for i, sh in enumerate(shapes):
+            nz, ny, nx = (sh, sh, sh) if np.isscalar(sh) else sh
+            dx = dxs[i] if dxs is not None else 2.0 / nx
+            x0 = x0s[i] if x0s is not None else (-0.5 * nx * dx, -0.5 * ny * dx, -0.5 * nz * dx)
+            self.cfgs[i] = make_config((nz, ny, nx), x0, dx, G, (0.0, 0.0, 0.0), lmax, "multipole", storage,
+                                       tblock, etas[i], self.stream.cuda_stream)
+        nb = _sz(0)
+        _check(_lib.hgs_workspace_bytes_batch(self.cfgs, n, ctypes.byref(nb)))
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        h = _vp()
+        _check(_lib.hgs_init_batch(self.cfgs, n, self.workspace.data_ptr(), nb.value, ctypes.byref(h)))
+        self._h = h
+        self.grids = []
+        for i in range(n):
+            c = _vp()
+            _check(_lib.hgs_batch_grid(self._h, i, ctypes.byref(c)))
+            self.grids.append(Solver._view(c, self.cfgs[i], dev, self.dtype, self.stream, self))
+
+    def step(self, rhos, c_g, dt, nsub: int) -> None:
+        n = self.n
+        for g, r in zip(self.grids, rhos):
+            g._need(r)
+        ptrs = (_vp * n)(*[r.data_ptr() for r in rhos])
+        cg = (ctypes.c_double * n)(*([float(c_g)] * n if np.isscalar(c_g) else [float(v) for v in c_g]))
+        dts = (ctypes.c_double * n)(*([float(dt)] * n if np.isscalar(dt) else [float(v) for v in dt]))
+        st = _lib.hgs_step_batch(self._h, ptrs, cg, dts, int(nsub))
+        if st != HGS_OK:
+            raise HGSError(st, _lib.hgs_batch_last_error(self._h).decode())
+
+    @property
+    def used_graph(self) -> bool:
+        return bool(_lib.hgs_batch_used_graph(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            for g in self.grids:
+                g._h = None
+            _lib.hgs_destroy_batch(self._h)
             self._h = None
 
     def __del__(self):

@@ -394,3 +394,54 @@ def test_tblock_against_oracle(gpu_lib, storage):
         s.step(to_dev(rho), 1.0, 0.4 * g.dx, 4)
         o.step(rho.astype(np.float64), 1.0, 0.4 * g.dx, 4)
     compare_state(s, o, storage, F64_TOL if storage == "f64" else F32_TOL)
+
+
+# ------------------------------------------------------------------ batched grids
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("tblock", [4, 1])
+def test_batch_bitwise_equals_single_grids(gpu_lib, storage, tblock):
+    """A batch of uneven grids stepped together (graph replay, fused launches
+    covering all grids) equals each grid stepped alone, bit for bit."""
+    import torch
+
+    shapes = [(32, 32, 32), (20, 24, 16), (48, 40, 64), (9, 11, 8), (64, 64, 64)]
+    b = gpu_lib.Batch(shapes, dxs=[grid_of(sh).dx for sh in shapes], x0s=[corner(sh) for sh in shapes],
+                      storage=storage, tblock=tblock, eta=0.3, lmax=4)
+    singles = [solver(gpu_lib, sh, storage=storage, tblock=tblock, eta=0.3, lmax=4) for sh in shapes]
+    rhos = [to_dev(dens(sh, 30 + i, storage)) for i, sh in enumerate(shapes)]
+    for dtf, nsub in [(0.4, 9), (0.4, 9), (0.3, 6)]:
+        dts = [dtf * grid_of(sh).dx for sh in shapes]
+        b.step(rhos, 1.0, dts, nsub)
+        for s, r, dt in zip(singles, rhos, dts):
+            s.step(r, 1.0, dt, nsub)
+    assert b.used_graph
+    torch.cuda.synchronize()
+    for g, s in zip(b.grids, singles):
+        ra, rb = g.save_raw(), s.save_raw()
+        assert torch.equal(ra[0], rb[0]) and torch.equal(ra[1], rb[1])
+
+
+def test_batch_against_oracle(gpu_lib):
+    shapes = [(24, 28, 32), (40, 36, 20)]
+    b = gpu_lib.Batch(shapes, dxs=[grid_of(sh).dx for sh in shapes], x0s=[corner(sh) for sh in shapes],
+                      storage="f64", tblock=4, eta=0.0, lmax=4)
+    rhos = [dens(sh, 40 + i, "f64") for i, sh in enumerate(shapes)]
+    oracles = [Oracle(grid_of(sh), lmax=4, eta=0.0) for sh in shapes]
+    for _ in range(3):
+        dts = [0.4 * grid_of(sh).dx for sh in shapes]
+        b.step([to_dev(r) for r in rhos], 1.0, dts, 5)
+        for o, r, dt in zip(oracles, rhos, dts):
+            o.step(r, 1.0, dt, 5)
+    for g, o in zip(b.grids, oracles):
+        compare_state(g, o, "f64", F64_TOL)
+
+
+def test_batch_rejects_bad_input(gpu_lib):
+    with pytest.raises(gpu_lib.HGSError):
+        gpu_lib.Batch([(8, 8, 10)], storage="f32")  # nx not a multiple of 4
+    b = gpu_lib.Batch([(8, 8, 8), (12, 12, 12)], storage="f32")
+    rhos = [to_dev(dens(sh, 1, "f32")) for sh in [(8, 8, 8), (12, 12, 12)]]
+    with pytest.raises(gpu_lib.HGSError) as ei:
+        b.step(rhos, 1.0, [0.4 * 0.25, 0.9 * 2 / 12], 3)  # CFL violated on grid 1
+    assert ei.value.status == gpu_lib.HGS_ERR_CFL
