@@ -1,0 +1,128 @@
+"""Pins of the FP64 network oracle (no GPU): finite differences, a direct
+correlation loop, closed forms for the transfer operators and Adam."""
+import numpy as np
+import pytest
+
+from oracle import nn
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def test_conv_matches_direct_loop():
+    a = _rand((1, 4, 5, 3, 2), 1)
+    w = _rand((27, 3, 2), 2)
+    b = _rand((3,), 3)
+    out = nn.conv3d(a, w, b)
+    B, Z, Y, X, C = a.shape
+    ref = np.zeros((1, Z, Y, X, 3))
+    for z in range(Z):
+        for y in range(Y):
+            for x in range(X):
+                for co in range(3):
+                    s = b[co]
+                    for t, (dz, dy, dx) in enumerate(nn.TAPS):
+                        zz, yy, xx = z + dz, y + dy, x + dx
+                        if 0 <= zz < Z and 0 <= yy < Y and 0 <= xx < X:
+                            s += np.dot(w[t, co], a[0, zz, yy, xx])
+                    ref[0, z, y, x, co] = s
+    assert np.allclose(out, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_conv_gradients_finite_differences():
+    a = _rand((2, 3, 4, 5, 3), 4)
+    w = _rand((27, 2, 3), 5)
+    b = _rand((2,), 6)
+    g = _rand((2, 3, 4, 5, 2), 7)
+    loss = lambda a_, w_, b_: np.sum(nn.conv3d(a_, w_, b_) * g)
+    ga = nn.conv3d_grad_input(g, w)
+    gw = nn.conv3d_grad_weight(a, g)
+    gb = nn.conv3d_grad_bias(g)
+    h = 1e-6
+    rng = np.random.default_rng(8)
+    for _ in range(12):
+        idx = tuple(rng.integers(0, s) for s in a.shape)
+        d = np.zeros_like(a)
+        d[idx] = h
+        fd = (loss(a + d, w, b) - loss(a - d, w, b)) / (2 * h)
+        assert fd == pytest.approx(ga[idx], rel=1e-7, abs=1e-7)
+    for _ in range(12):
+        idx = tuple(rng.integers(0, s) for s in w.shape)
+        d = np.zeros_like(w)
+        d[idx] = h
+        fd = (loss(a, w + d, b) - loss(a, w - d, b)) / (2 * h)
+        assert fd == pytest.approx(gw[idx], rel=1e-7, abs=1e-7)
+    for co in range(2):
+        d = np.zeros_like(b)
+        d[co] = h
+        fd = (loss(a, w, b + d) - loss(a, w, b - d)) / (2 * h)
+        assert fd == pytest.approx(gb[co], rel=1e-7, abs=1e-7)
+
+
+def test_network_backward_finite_differences():
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((1, 4, 4, 4, 2))
+    layers = [(0.3 * rng.standard_normal((27, 3, 2)), 0.1 * rng.standard_normal(3)),
+              (0.3 * rng.standard_normal((27, 3, 3)), 0.1 * rng.standard_normal(3)),
+              (0.3 * rng.standard_normal((27, 2, 3)), 0.1 * rng.standard_normal(2))]
+    tgt = rng.standard_normal((1, 4, 4, 4, 2))
+
+    def loss(ls):
+        out = nn.forward(x, ls)[-1]
+        return 0.5 * np.sum((out - tgt) ** 2)
+
+    acts = nn.forward(x, layers)
+    grads = nn.backward(acts, layers, acts[-1] - tgt)
+    h = 1e-6
+    for li in range(3):
+        for _ in range(6):
+            idx = tuple(rng.integers(0, s) for s in layers[li][0].shape)
+            lp = [(w.copy(), b.copy()) for w, b in layers]
+            lm = [(w.copy(), b.copy()) for w, b in layers]
+            lp[li][0][idx] += h
+            lm[li][0][idx] -= h
+            fd = (loss(lp) - loss(lm)) / (2 * h)
+            assert fd == pytest.approx(grads[li][0][idx], rel=1e-6, abs=1e-8)
+
+
+def test_restrict_and_prolong_closed_forms():
+    n = 8
+    c = (np.arange(n) + 0.5) / n  # coarse cell centres on [0, 1]
+    f = (np.arange(2 * n) + 0.5) / (2 * n)
+    Zc, Yc, Xc = np.meshgrid(c, c, c, indexing="ij")
+    Zf, Yf, Xf = np.meshgrid(f, f, f, indexing="ij")
+    lin = lambda X, Y, Z: 1.5 * X - 0.7 * Y + 0.2 * Z + 0.3
+    # prolongation is exact on linear fields (including the extrapolated faces)
+    assert np.allclose(nn.prolong2(lin(Xc, Yc, Zc)), lin(Xf, Yf, Zf), rtol=0, atol=1e-13)
+    # restriction of a linear field equals the field at coarse centres
+    assert np.allclose(nn.restrict2(lin(Xf, Yf, Zf)), lin(Xc, Yc, Zc), rtol=0, atol=1e-13)
+    # along one axis, restriction after prolongation is the stencil 3/4 c_i + 1/8 (c_{i-1} + c_{i+1})
+    r = np.random.default_rng(3).standard_normal(9)
+    field = np.broadcast_to(r, (2, 2, 9)).copy()
+    rp = nn.restrict2(nn.prolong2(field))[0, 0]
+    assert np.allclose(rp[1:-1], 0.75 * r[1:-1] + 0.125 * (r[:-2] + r[2:]), rtol=0, atol=1e-14)
+    # interior weights 3/4, 1/4 along one axis
+    e = np.zeros((3, 3, 3))
+    e[1, 1, 1] = 1.0
+    p = nn.prolong2(e)
+    assert p[2, 2, 2] == pytest.approx(0.75 ** 3)
+    assert p[1, 2, 2] == pytest.approx(0.25 * 0.75 ** 2)
+
+
+def test_adam_matches_closed_form_first_step():
+    p = np.array([1.0, -2.0])
+    g = np.array([0.5, -3.0])
+    p1, m, v = nn.adam(p, np.zeros(2), np.zeros(2), g, 1, lr=0.1)
+    # at t = 1 the bias-corrected step is lr * sign(g) (up to eps)
+    assert np.allclose(p1, p - 0.1 * np.sign(g), rtol=0, atol=1e-7)
+
+
+def test_bf16_round():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 3.14159265], dtype=np.float32)
+    r = nn.bf16_round(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0  # tie goes to even
+    assert r[2] == 1.0 + 2 ** -6
+    assert r[3] == -2.5
+    assert abs(r[4] - 3.140625) < 1e-12
