@@ -205,6 +205,57 @@ int32_t hgs_batch_used_graph(const hgs_batch* b);
 const char* hgs_batch_last_error(const hgs_batch* b);
 hgs_status hgs_destroy_batch(hgs_batch* b);
 
+/* ---- Learned warm start: network kernels ---------------------------------
+ * An extension of the method (the paper starts its runs from a Poisson
+ * solution, Sec. 2): a 3x3x3 convolution network predicts the potential from
+ * the density and a coarse solve, and the solver continues from it.  Tensors
+ * are channels-last with 16 channels, (B, Z, Y, X, 16), bfloat16 bit patterns
+ * in uint16 unless stated; weights are (27 taps, 16 out, 16 in) bfloat16 with
+ * tap t = (dz+1)*9 + (dy+1)*3 + (dx+1); the convolution is a correlation with
+ * zero padding ("same" size): out[v][co] = sum_t,ci w[t][co][ci] in[v+tap][ci].
+ * All pointers are device pointers; all calls are asynchronous on `stream`. */
+#define HGS_NN_CHANNELS 16
+typedef enum {
+    HGS_NN_F32 = 0,        /* out (FP32) = conv + bias */
+    HGS_NN_TANH_BF16 = 1,  /* out (bf16) = tanh(conv + bias) */
+    HGS_NN_DTANH_BF16 = 2, /* out (bf16) = conv * (1 - aux^2), aux a tanh output (backward) */
+    HGS_NN_BF16 = 3        /* out (bf16) = conv + bias */
+} hgs_nn_mode;
+/* X must be a multiple of 16; bias may be NULL (zero); aux only for DTANH. */
+hgs_status hgs_nn_conv3d(const uint16_t* in, const uint16_t* w, const float* bias, int32_t B, int32_t Z, int32_t Y,
+                         int32_t X, int32_t mode, const uint16_t* aux, void* out, void* stream);
+/* wt[26 - t][ci][co] = w[t][co][ci]: the weights of the input-gradient convolution. */
+hgs_status hgs_nn_flip_weights(const uint16_t* w, uint16_t* wt, void* stream);
+/* Weight and bias gradients dw[t][co][ci] = sum_v g[v][co] a[v+tap][ci] (FP32),
+ * db[co] = sum_v g[v][co]; X a multiple of 16 and at most 128.  Needs a device
+ * workspace of hgs_nn_wgrad_workspace_bytes(). Fixed-order reductions. */
+hgs_status hgs_nn_wgrad_workspace_bytes(int32_t B, int32_t Z, int32_t Y, int32_t X, size_t* bytes);
+hgs_status hgs_nn_wgrad(const uint16_t* a, const uint16_t* g, int32_t B, int32_t Z, int32_t Y, int32_t X, float* dw,
+                        float* db, void* workspace, size_t bytes, void* stream);
+/* Planar FP32 fields [B][C][nvox] <-> channels-last (bf16 out / FP32 in), C <= 16. */
+hgs_status hgs_nn_pack(const float* fields, int32_t B, int32_t C, int64_t nvox, uint16_t* out, void* stream);
+hgs_status hgs_nn_unpack(const float* in, int32_t B, int32_t C, int64_t nvox, float* fields, void* stream);
+/* Mean-squared error of the first C channels of out (FP32 channels-last)
+ * against planar targets [B][C][nvox]: grad (bf16 channels-last, zero beyond
+ * C) = 2 (out - target) / (B C nvox); *loss_dev (device double) = sum of
+ * squares.  Needs a device workspace of HGS_NN_MSE_PARTIALS doubles. */
+#define HGS_NN_MSE_PARTIALS 1024
+hgs_status hgs_nn_mse(const float* out, const float* target, int32_t B, int32_t C, int64_t nvox, uint16_t* grad,
+                      double* loss_dev, double* partials, void* stream);
+/* Adam with bias correction (step t >= 1) on FP32 master parameters; p16
+ * (nullable) receives their bfloat16 copy. */
+hgs_status hgs_nn_adam(float* p, float* m, float* v, const float* g, uint16_t* p16, int32_t n, float lr, float b1,
+                       float b2, float eps, int32_t t, void* stream);
+/* [B][2cz][2cy][2cx] <-> [B][cz][cy][cx]: 2x2x2 mean restriction, and
+ * cell-centred trilinear prolongation (weights 3/4, 1/4 per axis; linear
+ * extrapolation, 5/4 and -1/4, at the faces).  dtype: hgs_dtype. */
+hgs_status hgs_nn_restrict2(const void* fine, void* coarse, int32_t B, int32_t cz, int32_t cy, int32_t cx,
+                            int32_t dtype, void* stream);
+hgs_status hgs_nn_prolong2(const void* coarse, void* fine, int32_t B, int32_t cz, int32_t cy, int32_t cx,
+                           int32_t dtype, void* stream);
+/* Reason for the last non-OK status of an hgs_nn_* call on this thread. */
+const char* hgs_nn_last_error(void);
+
 /* Release the host context (the workspace stays the caller's).  NULL is a no-op. */
 hgs_status hgs_destroy(hgs_ctx* ctx);
 

@@ -1,0 +1,168 @@
+// Host side of the hgs_nn_* entry points (learned warm start) of include/hgs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "../../include/hgs.h"
+#include "k_nn.hpp"
+
+using namespace hgs::nn;
+
+namespace {
+
+thread_local std::string g_nn_err;
+
+hgs_status nfail(hgs_status s, const std::string& m) {
+    g_nn_err = m;
+    return s;
+}
+
+hgs_status nlaunched(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return nfail(HGS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return HGS_OK;
+}
+
+bool dims_ok(int32_t B, int32_t Z, int32_t Y, int32_t X) {
+    return B >= 1 && Z >= 1 && Y >= 1 && X >= 16 && X % 16 == 0 && (int64_t)B * Z * Y * X <= ((int64_t)1 << 31);
+}
+
+int wgrad_blocks(int32_t B, int32_t Z, int32_t Y) {
+    const int64_t rows = (int64_t)B * Z * Y;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(512, (rows + 3) / 4));
+}
+
+int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256)); }
+
+}  // namespace
+
+extern "C" {
+
+const char* hgs_nn_last_error(void) { return g_nn_err.c_str(); }
+
+hgs_status hgs_nn_conv3d(const uint16_t* in, const uint16_t* w, const float* bias, int32_t B, int32_t Z, int32_t Y,
+                         int32_t X, int32_t mode, const uint16_t* aux, void* out, void* stream) {
+    if (!in || !w || !out) return nfail(HGS_ERR_ARG, "in, w and out must be non-NULL");
+    if (!dims_ok(B, Z, Y, X)) return nfail(HGS_ERR_ARG, "need B, Z, Y >= 1 and X a positive multiple of 16");
+    if (mode < 0 || mode > 3) return nfail(HGS_ERR_ARG, "mode must be 0..3");
+    if (mode == HGS_NN_DTANH_BF16 && !aux) return nfail(HGS_ERR_ARG, "DTANH needs aux");
+    (void)hipGetLastError();
+    const int64_t waves = (int64_t)B * Z * Y * (X / 16);
+    const int64_t blocks = (waves + 3) / 4;
+    if (blocks > 0x7fffffff) return nfail(HGS_ERR_ARG, "tensor too large");
+    hipLaunchKernelGGL(k_conv3d, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), in, w, bias, B,
+                       Z, Y, X, mode, aux, out);
+    return nlaunched("hgs_nn_conv3d");
+}
+
+hgs_status hgs_nn_flip_weights(const uint16_t* w, uint16_t* wt, void* stream) {
+    if (!w || !wt) return nfail(HGS_ERR_ARG, "w and wt must be non-NULL");
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_flip_weights, dim3((27 * NC * NC + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), w, wt);
+    return nlaunched("hgs_nn_flip_weights");
+}
+
+hgs_status hgs_nn_wgrad_workspace_bytes(int32_t B, int32_t Z, int32_t Y, int32_t X, size_t* bytes) {
+    if (!bytes) return nfail(HGS_ERR_ARG, "bytes is NULL");
+    if (!dims_ok(B, Z, Y, X) || X > WG_MAXX) return nfail(HGS_ERR_ARG, "need X a multiple of 16 and at most 128");
+    *bytes = (size_t)wgrad_blocks(B, Z, Y) * 4 * (27 * NC * NC + NC) * sizeof(float);
+    return HGS_OK;
+}
+
+hgs_status hgs_nn_wgrad(const uint16_t* a, const uint16_t* g, int32_t B, int32_t Z, int32_t Y, int32_t X, float* dw,
+                        float* db, void* workspace, size_t bytes, void* stream) {
+    size_t need = 0;
+    hgs_status s = hgs_nn_wgrad_workspace_bytes(B, Z, Y, X, &need);
+    if (s != HGS_OK) return s;
+    if (!a || !g || !dw || !db) return nfail(HGS_ERR_ARG, "a, g, dw and db must be non-NULL");
+    if (!workspace || bytes < need) return nfail(HGS_ERR_WORKSPACE, "workspace smaller than hgs_nn_wgrad_workspace_bytes()");
+    (void)hipGetLastError();
+    const int nb = wgrad_blocks(B, Z, Y);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_wgrad_partial, dim3(nb), dim3(256), 0, st, a, g, B, Z, Y, X, static_cast<float*>(workspace));
+    hipLaunchKernelGGL(k_wgrad_final, dim3((27 * NC * NC + NC + 255) / 256), dim3(256), 0, st,
+                       static_cast<const float*>(workspace), nb * 4, dw, db);
+    return nlaunched("hgs_nn_wgrad");
+}
+
+hgs_status hgs_nn_pack(const float* fields, int32_t B, int32_t C, int64_t nvox, uint16_t* out, void* stream) {
+    if (!fields || !out) return nfail(HGS_ERR_ARG, "fields and out must be non-NULL");
+    if (B < 1 || C < 1 || C > NC || nvox < 1) return nfail(HGS_ERR_ARG, "need B >= 1, 1 <= C <= 16, nvox >= 1");
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_pack, dim3(grid_of((int64_t)B * nvox)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       fields, B, C, nvox, out);
+    return nlaunched("hgs_nn_pack");
+}
+
+hgs_status hgs_nn_unpack(const float* in, int32_t B, int32_t C, int64_t nvox, float* fields, void* stream) {
+    if (!fields || !in) return nfail(HGS_ERR_ARG, "in and fields must be non-NULL");
+    if (B < 1 || C < 1 || C > NC || nvox < 1) return nfail(HGS_ERR_ARG, "need B >= 1, 1 <= C <= 16, nvox >= 1");
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_unpack, dim3(grid_of((int64_t)B * nvox)), dim3(256), 0, static_cast<hipStream_t>(stream), in,
+                       B, C, nvox, fields);
+    return nlaunched("hgs_nn_unpack");
+}
+
+hgs_status hgs_nn_mse(const float* out, const float* target, int32_t B, int32_t C, int64_t nvox, uint16_t* grad,
+                      double* loss_dev, double* partials, void* stream) {
+    if (!out || !target || !grad || !loss_dev || !partials) return nfail(HGS_ERR_ARG, "NULL argument");
+    if (B < 1 || C < 1 || C > NC || nvox < 1) return nfail(HGS_ERR_ARG, "need B >= 1, 1 <= C <= 16, nvox >= 1");
+    (void)hipGetLastError();
+    const int nb = std::min(HGS_NN_MSE_PARTIALS, grid_of((int64_t)B * nvox));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float inv = (float)(1.0 / ((double)B * C * nvox));
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, out, target, B, C, nvox, inv, grad, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, partials, nb, loss_dev);
+    return nlaunched("hgs_nn_mse");
+}
+
+hgs_status hgs_nn_adam(float* p, float* m, float* v, const float* g, uint16_t* p16, int32_t n, float lr, float b1,
+                       float b2, float eps, int32_t t, void* stream) {
+    if (!p || !m || !v || !g) return nfail(HGS_ERR_ARG, "p, m, v and g must be non-NULL");
+    if (n < 1 || t < 1 || !(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+        return nfail(HGS_ERR_ARG, "need n >= 1, t >= 1, lr > 0, 0 <= b1, b2 < 1, eps > 0");
+    (void)hipGetLastError();
+    const float c1 = (float)(1.0 - std::pow((double)b1, t)), c2 = (float)(1.0 - std::pow((double)b2, t));
+    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream), p, m, v, g, p16, n,
+                       lr, b1, b2, eps, c1, c2);
+    return nlaunched("hgs_nn_adam");
+}
+
+hgs_status hgs_nn_restrict2(const void* fine, void* coarse, int32_t B, int32_t cz, int32_t cy, int32_t cx,
+                            int32_t dtype, void* stream) {
+    if (!fine || !coarse) return nfail(HGS_ERR_ARG, "fine and coarse must be non-NULL");
+    if (B < 1 || cz < 1 || cy < 1 || cx < 1 || (dtype != HGS_F32 && dtype != HGS_F64))
+        return nfail(HGS_ERR_ARG, "bad sizes or dtype");
+    (void)hipGetLastError();
+    const int64_t n = (int64_t)B * cz * cy * cx;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == HGS_F32)
+        hipLaunchKernelGGL(k_restrict2<float>, dim3(grid_of(n)), dim3(256), 0, st, static_cast<const float*>(fine), B,
+                           cz, cy, cx, static_cast<float*>(coarse));
+    else
+        hipLaunchKernelGGL(k_restrict2<double>, dim3(grid_of(n)), dim3(256), 0, st, static_cast<const double*>(fine),
+                           B, cz, cy, cx, static_cast<double*>(coarse));
+    return nlaunched("hgs_nn_restrict2");
+}
+
+hgs_status hgs_nn_prolong2(const void* coarse, void* fine, int32_t B, int32_t cz, int32_t cy, int32_t cx,
+                           int32_t dtype, void* stream) {
+    if (!fine || !coarse) return nfail(HGS_ERR_ARG, "fine and coarse must be non-NULL");
+    if (B < 1 || cz < 1 || cy < 1 || cx < 1 || (dtype != HGS_F32 && dtype != HGS_F64))
+        return nfail(HGS_ERR_ARG, "bad sizes or dtype");
+    (void)hipGetLastError();
+    const int64_t n = (int64_t)B * 8 * cz * cy * cx;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == HGS_F32)
+        hipLaunchKernelGGL(k_prolong2<float>, dim3(grid_of(n)), dim3(256), 0, st, static_cast<const float*>(coarse), B,
+                           cz, cy, cx, static_cast<float*>(fine));
+    else
+        hipLaunchKernelGGL(k_prolong2<double>, dim3(grid_of(n)), dim3(256), 0, st, static_cast<const double*>(coarse),
+                           B, cz, cy, cx, static_cast<double*>(fine));
+    return nlaunched("hgs_nn_prolong2");
+}
+
+}  // extern "C"

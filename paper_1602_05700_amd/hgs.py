@@ -76,6 +76,18 @@ _SIGS = {
     "hgs_batch_used_graph": (_i32, [_vp]),
     "hgs_batch_last_error": (_cp, [_vp]),
     "hgs_destroy_batch": (_i32, [_vp]),
+    "hgs_nn_conv3d": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "hgs_nn_flip_weights": (_i32, [_vp, _vp, _vp]),
+    "hgs_nn_wgrad_workspace_bytes": (_i32, [_i32, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
+    "hgs_nn_wgrad": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "hgs_nn_pack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
+    "hgs_nn_unpack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
+    "hgs_nn_mse": (_i32, [_vp, _vp, _i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]),
+    "hgs_nn_adam": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _i32, _vp]),
+    "hgs_nn_restrict2": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
+    "hgs_nn_prolong2": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
+    "hgs_nn_last_error": (_cp, []),
     "hgs_destroy": (_i32, [_vp]),
     "hgs_status_str": (_cp, [_i32]),
     "hgs_last_error": (_cp, [_vp]),
@@ -366,3 +378,96 @@ def flat_to_faces(flat, shape):
         out.append(np.asarray(flat[o:o + s]).reshape(sh))
         o += s
     return out
+
+
+# ---------------------------------------------------------------------------
+# Network kernels of the learned warm start (channels-last, 16 channels,
+# torch.bfloat16 tensors carry the bfloat16 bit patterns)
+NN_F32, NN_TANH_BF16, NN_DTANH_BF16, NN_BF16 = 0, 1, 2, 3
+NN_CHANNELS = 16
+NN_MSE_PARTIALS = 1024
+
+
+def _nn_check(st):
+    if st != HGS_OK:
+        raise HGSError(st, _lib.hgs_nn_last_error().decode())
+
+
+def _stream_of(t):
+    import torch
+
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def nn_conv3d(inp, w, bias, out, mode: int, aux=None):
+    """inp: (B,Z,Y,X,16) bf16; w: (27,16,16) bf16; bias: (16,) fp32 or None;
+    out: (B,Z,Y,X,16) fp32 (mode 0) or bf16."""
+    B, Z, Y, X, C = inp.shape
+    assert C == NN_CHANNELS and inp.is_contiguous() and out.is_contiguous() and w.is_contiguous()
+    _nn_check(_lib.hgs_nn_conv3d(inp.data_ptr(), w.data_ptr(), _ptr(bias), B, Z, Y, X, int(mode), _ptr(aux),
+                                 out.data_ptr(), _stream_of(inp)))
+    return out
+
+
+def nn_flip_weights(w, wt):
+    _nn_check(_lib.hgs_nn_flip_weights(w.data_ptr(), wt.data_ptr(), _stream_of(w)))
+    return wt
+
+
+def nn_wgrad(a, g, dw, db, workspace=None):
+    import torch
+
+    B, Z, Y, X, C = a.shape
+    nb = _sz(0)
+    _nn_check(_lib.hgs_nn_wgrad_workspace_bytes(B, Z, Y, X, ctypes.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(nb.value, dtype=torch.uint8, device=a.device)
+    _nn_check(_lib.hgs_nn_wgrad(a.data_ptr(), g.data_ptr(), B, Z, Y, X, dw.data_ptr(), db.data_ptr(),
+                                workspace.data_ptr(), workspace.numel(), _stream_of(a)))
+    return workspace
+
+
+def nn_pack(fields, out):
+    """fields: (B, C, *spatial) fp32 -> out (B, *spatial, 16) bf16."""
+    B, C = fields.shape[:2]
+    nvox = fields[0, 0].numel()
+    _nn_check(_lib.hgs_nn_pack(fields.data_ptr(), B, C, nvox, out.data_ptr(), _stream_of(fields)))
+    return out
+
+
+def nn_unpack(inp, C, fields):
+    B = inp.shape[0]
+    nvox = inp[0].numel() // NN_CHANNELS
+    _nn_check(_lib.hgs_nn_unpack(inp.data_ptr(), B, C, nvox, fields.data_ptr(), _stream_of(inp)))
+    return fields
+
+
+def nn_mse(out, target, grad, loss_dev, partials):
+    B, C = target.shape[:2]
+    nvox = target[0, 0].numel()
+    _nn_check(_lib.hgs_nn_mse(out.data_ptr(), target.data_ptr(), B, C, nvox, grad.data_ptr(), loss_dev.data_ptr(),
+                              partials.data_ptr(), _stream_of(out)))
+
+
+def nn_adam(p, m, v, g, p16, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    _nn_check(_lib.hgs_nn_adam(p.data_ptr(), m.data_ptr(), v.data_ptr(), g.data_ptr(), _ptr(p16), p.numel(),
+                               float(lr), float(b1), float(b2), float(eps), int(t), _stream_of(p)))
+
+
+def nn_restrict2(fine, coarse):
+    """fine (B, 2cz, 2cy, 2cx) -> coarse (B, cz, cy, cx); fp32 or fp64."""
+    import torch
+
+    B, cz, cy, cx = coarse.shape
+    dt = HGS_F32 if coarse.dtype == torch.float32 else HGS_F64
+    _nn_check(_lib.hgs_nn_restrict2(fine.data_ptr(), coarse.data_ptr(), B, cz, cy, cx, dt, _stream_of(fine)))
+    return coarse
+
+
+def nn_prolong2(coarse, fine):
+    import torch
+
+    B, cz, cy, cx = coarse.shape
+    dt = HGS_F32 if coarse.dtype == torch.float32 else HGS_F64
+    _nn_check(_lib.hgs_nn_prolong2(coarse.data_ptr(), fine.data_ptr(), B, cz, cy, cx, dt, _stream_of(coarse)))
+    return fine

@@ -1,0 +1,149 @@
+"""GPU network kernels (learned warm start) against the FP64 network oracle.
+
+Inputs and weights are rounded to bfloat16 on the host and the oracle is fed
+the same rounded values, so FP32 outputs differ only by accumulation order
+(tolerance 2e-5 relative to the largest magnitude); bfloat16 outputs are
+compared within one bfloat16 rounding (2^-8 relative) of the oracle value.
+"""
+import numpy as np
+import pytest
+
+from oracle import nn
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x, dtype):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda").to(dtype)
+
+
+def _h(t):
+    import torch
+
+    return t.detach().double().cpu().numpy()
+
+
+def _rand_bf(shape, seed, scale=1.0):
+    r = np.random.default_rng(seed).standard_normal(shape) * scale
+    return nn.bf16_round(r.astype(np.float32))
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+SHAPES = [(1, 3, 4, 16), (2, 6, 5, 32), (1, 8, 8, 64)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_conv3d_forward_modes(gpu_lib, shape):
+    import torch
+
+    hgs = gpu_lib
+    B, Z, Y, X = shape
+    a = _rand_bf((B, Z, Y, X, 16), 1)
+    w = _rand_bf((27, 16, 16), 2, 0.2)
+    b = np.random.default_rng(3).standard_normal(16).astype(np.float32).astype(np.float64)
+    ta, tw, tb = _t(a, torch.bfloat16), _t(w, torch.bfloat16), _t(b, torch.float32)
+    ref = nn.conv3d(a, w, b)
+    out = torch.empty((B, Z, Y, X, 16), dtype=torch.float32, device="cuda")
+    hgs.nn_conv3d(ta, tw, tb, out, hgs.NN_F32)
+    assert rel(_h(out), ref) < 2e-5
+    o16 = torch.empty((B, Z, Y, X, 16), dtype=torch.bfloat16, device="cuda")
+    hgs.nn_conv3d(ta, tw, tb, o16, hgs.NN_TANH_BF16)
+    tr = np.tanh(ref)
+    assert np.all(np.abs(_h(o16) - tr) <= 2 ** -8 * np.abs(tr) + 1e-6)
+    aux = _rand_bf((B, Z, Y, X, 16), 4, 0.5)
+    hgs.nn_conv3d(ta, tw, None, o16, hgs.NN_DTANH_BF16, aux=_t(aux, torch.bfloat16))
+    dr = nn.conv3d(a, w) * (1 - aux * aux)
+    assert np.all(np.abs(_h(o16) - dr) <= 2 ** -8 * np.abs(dr) + 1e-4 * np.max(np.abs(dr)))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_conv3d_input_gradient_by_flipped_weights(gpu_lib, shape):
+    import torch
+
+    hgs = gpu_lib
+    B, Z, Y, X = shape
+    g = _rand_bf((B, Z, Y, X, 16), 5)
+    w = _rand_bf((27, 16, 16), 6, 0.2)
+    tw = _t(w, torch.bfloat16)
+    wt = torch.empty_like(tw)
+    hgs.nn_flip_weights(tw, wt)
+    out = torch.empty((B, Z, Y, X, 16), dtype=torch.float32, device="cuda")
+    hgs.nn_conv3d(_t(g, torch.bfloat16), wt, None, out, hgs.NN_F32)
+    assert rel(_h(out), nn.conv3d_grad_input(g, w)) < 2e-5
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(3, 5, 7, 48)])
+def test_conv3d_weight_gradient(gpu_lib, shape):
+    import torch
+
+    hgs = gpu_lib
+    B, Z, Y, X = shape
+    a = _rand_bf((B, Z, Y, X, 16), 7)
+    g = _rand_bf((B, Z, Y, X, 16), 8)
+    dw = torch.empty((27, 16, 16), dtype=torch.float32, device="cuda")
+    db = torch.empty(16, dtype=torch.float32, device="cuda")
+    hgs.nn_wgrad(_t(a, torch.bfloat16), _t(g, torch.bfloat16), dw, db)
+    assert rel(_h(dw), nn.conv3d_grad_weight(a, g)) < 2e-5
+    assert rel(_h(db), nn.conv3d_grad_bias(g)) < 2e-5
+
+
+def test_transfer_operators(gpu_lib):
+    import torch
+
+    hgs = gpu_lib
+    rng = np.random.default_rng(9)
+    for cz, cy, cx in [(1, 1, 1), (2, 3, 5), (8, 8, 8), (16, 12, 20)]:
+        f = rng.standard_normal((2, 2 * cz, 2 * cy, 2 * cx))
+        c = torch.empty((2, cz, cy, cx), dtype=torch.float64, device="cuda")
+        hgs.nn_restrict2(_t(f, torch.float64), c)
+        assert np.allclose(_h(c), nn.restrict2(f), rtol=0, atol=1e-14)
+        cc = rng.standard_normal((2, cz, cy, cx))
+        fo = torch.empty((2, 2 * cz, 2 * cy, 2 * cx), dtype=torch.float64, device="cuda")
+        hgs.nn_prolong2(_t(cc, torch.float64), fo)
+        if min(cz, cy, cx) > 1:
+            assert np.allclose(_h(fo), nn.prolong2(cc), rtol=0, atol=1e-13)
+
+
+def test_adam_mse_pack(gpu_lib):
+    import torch
+
+    hgs = gpu_lib
+    rng = np.random.default_rng(10)
+    n = 1000
+    p = rng.standard_normal(n).astype(np.float32)
+    g = rng.standard_normal(n).astype(np.float32)
+    tp, tm, tv = _t(p, torch.float32), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    p16 = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    pp, mm, vv = p.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t in (1, 2, 3):
+        hgs.nn_adam(tp, tm, tv, _t(g, torch.float32), p16, 1e-2, t)
+        pp, mm, vv = nn.adam(pp, mm, vv, g.astype(np.float64), t, lr=1e-2)
+    assert np.allclose(_h(tp), pp, rtol=0, atol=1e-5)
+    assert np.array_equal(_h(p16), nn.bf16_round(_h(tp).astype(np.float32)))
+    # pack / mse / unpack
+    B, C = 2, 3
+    fields = rng.standard_normal((B, C, 4, 5, 16)).astype(np.float32)
+    packed = torch.empty((B, 4, 5, 16, 16), dtype=torch.bfloat16, device="cuda")
+    hgs.nn_pack(_t(fields, torch.float32), packed)
+    ph = _h(packed)
+    assert np.array_equal(ph[..., :C], np.moveaxis(nn.bf16_round(fields), 1, -1))
+    assert np.all(ph[..., C:] == 0)
+    out = _t(rng.standard_normal((B, 4, 5, 16, 16)).astype(np.float32), torch.float32)
+    tgt = rng.standard_normal((B, C, 4, 5, 16)).astype(np.float32)
+    grad = torch.empty((B, 4, 5, 16, 16), dtype=torch.bfloat16, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    parts = torch.empty(hgs.NN_MSE_PARTIALS, dtype=torch.float64, device="cuda")
+    hgs.nn_mse(out, _t(tgt, torch.float32), grad, loss, parts)
+    d = np.moveaxis(_h(out)[..., :C], -1, 1) - tgt
+    assert float(loss.item()) == pytest.approx(np.sum(d * d), rel=1e-6)  # differences formed in FP32
+    gh = _h(grad)
+    assert np.allclose(np.moveaxis(gh[..., :C], -1, 1), nn.bf16_round((2 * d / d.size).astype(np.float32)), rtol=0,
+                       atol=1e-12)
+    back = torch.empty((B, C, 4, 5, 16), dtype=torch.float32, device="cuda")
+    hgs.nn_unpack(out, C, back)
+    assert np.array_equal(_h(back), np.moveaxis(_h(out)[..., :C], -1, 1))
