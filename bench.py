@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--nsub", type=int, default=4)
-    ap.add_argument("--tblock", type=int, default=0, help="substeps per fused launch (0 = library default)")
+    ap.add_argument("--tblock", type=int, default=0, help="substeps per fused launch (0 = autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -164,7 +164,14 @@ def main():
     log(f"[bench] generating {W + K} rotated densities {n}^3 fp32 on the GPU")
     rhos = [workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * h), dev, torch.float32)
             for h in range(W + K)]
-    s = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=args.tblock, device=dev)
+    tune = None
+    tblock = args.tblock
+    if tblock == 0:
+        best, times = hgs.autotune(n, rhos[0], c_g, dt, nsub, storage="f32", lmax=4, device=dev)
+        tune = {"best_tblock": best, "ms_per_substep": times}
+        tblock = best
+        log(f"[bench] autotune: depth {best}, ms per substep {times}")
+    s = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=tblock, device=dev)
     out = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in range(3)]
     stream = s.stream
 
@@ -233,6 +240,7 @@ def main():
             "algorithmic_bytes_per_launch": per_launch_bytes,
             "avg_launch_us": round(avg_s * 1e6, 2),
         },
+        "autotune": tune,
         "kernels_us_per_step": {
             "stencil": round(st["ms"] / K * 1e3, 1),
             "multipole": round(mp["ms"] / K * 1e3, 1),

@@ -256,6 +256,19 @@ hgs_status hgs_nn_prolong2(const void* coarse, void* fine, int32_t B, int32_t cz
 /* Reason for the last non-OK status of an hgs_nn_* call on this thread. */
 const char* hgs_nn_last_error(void);
 
+/* ---- Autotuner -------------------------------------------------------------
+ * Picks the fused depth (substeps per stencil launch) for a configuration by
+ * timing whole hydrodynamical steps, hgs_step(rho, c_g, dt, nsub), with HIP
+ * events for every depth 1..HGS_TMAX on a temporary context built over the
+ * caller's workspace (hgs_workspace_bytes(cfg) bytes; its contents are
+ * overwritten).  Synchronises.  *best_tblock receives the fastest depth;
+ * ms_per_substep (nullable, HGS_TMAX entries) the measured time per substep for
+ * depths 1..HGS_TMAX.  If the environment variable HGS_TUNE_CACHE names a
+ * file, results are cached there per (device architecture, nx, ny, nz, storage,
+ * nsub, bc) and a cached entry is returned without timing (times set to -1). */
+hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, double c_g, double dt, int32_t nsub,
+                        void* workspace, size_t bytes, int32_t* best_tblock, double* ms_per_substep);
+
 /* Release the host context (the workspace stays the caller's).  NULL is a no-op. */
 hgs_status hgs_destroy(hgs_ctx* ctx);
 

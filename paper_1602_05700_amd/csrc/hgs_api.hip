@@ -22,7 +22,10 @@
 #include "k_tblock.hpp"
 #include "k_batch.hpp"
 #include <algorithm>
+#include <cstdlib>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <tuple>
 
 using namespace hgs;
@@ -1143,3 +1146,106 @@ hgs_status hgs_destroy_batch(hgs_batch* b) {
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Autotuner
+// ============================================================================
+
+namespace {
+
+std::string tune_key(const hgs_config* cfg, int nsub) {
+    hipDeviceProp_t p;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) {
+        arch = p.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch = arch.substr(0, colon);
+    }
+    std::ostringstream k;
+    k << arch << ' ' << cfg->nx << ' ' << cfg->ny << ' ' << cfg->nz << ' ' << (cfg->storage == HGS_F64 ? "f64" : "f32")
+      << ' ' << nsub << ' ' << (cfg->bc == HGS_BC_USER ? "user" : "multipole");
+    return k.str();
+}
+
+// cache file: one "<key> <tblock>" entry per line
+int tune_cache_lookup(const std::string& path, const std::string& key) {
+    std::ifstream f(path);
+    std::string line;
+    int best = 0;
+    while (std::getline(f, line)) {
+        if (line.size() > key.size() && line.compare(0, key.size(), key) == 0 && line[key.size()] == ' ') {
+            const int t = std::atoi(line.c_str() + key.size() + 1);
+            if (t >= 1 && t <= HGS_TMAX) best = t;  // last entry wins
+        }
+    }
+    return best;
+}
+
+void tune_cache_store(const std::string& path, const std::string& key, int t) {
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << ' ' << t << '\n';
+}
+
+}  // namespace
+
+extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, double c_g, double dt, int32_t nsub,
+                                   void* workspace, size_t bytes, int32_t* best_tblock, double* ms_per_substep) {
+    std::string why;
+    hgs_status s = check_config(cfg, why);
+    if (s != HGS_OK) return fail(nullptr, s, why);
+    if (!best_tblock) return fail(nullptr, HGS_ERR_ARG, "best_tblock is NULL");
+    s = validate_step(nullptr, cfg, rho, c_g, dt, nsub);
+    if (s != HGS_OK) return s;
+    const char* cache = std::getenv("HGS_TUNE_CACHE");
+    const std::string key = tune_key(cfg, nsub);
+    if (cache && *cache) {
+        const int t = tune_cache_lookup(cache, key);
+        if (t > 0) {
+            *best_tblock = t;
+            if (ms_per_substep)
+                for (int i = 0; i < HGS_TMAX; ++i) ms_per_substep[i] = -1.0;
+            return HGS_OK;
+        }
+    }
+    hgs_ctx* c = nullptr;
+    s = hgs_init(cfg, workspace, bytes, &c);
+    if (s != HGS_OK) return s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        hgs_destroy(c);
+        return fail(nullptr, HGS_ERR_DEVICE, "hgs_autotune: event creation failed");
+    }
+    const int reps = 3;
+    double best_ms = -1.0;
+    int best = 1;
+    hgs_status st = HGS_OK;
+    for (int t = 1; t <= HGS_TMAX && st == HGS_OK; ++t) {
+        c->tblock = t;
+        st = hgs_step(c, rho, c_g, dt, nsub);  // warm-up
+        if (st != HGS_OK) break;
+        (void)hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps && st == HGS_OK; ++r) st = hgs_step(c, rho, c_g, dt, nsub);
+        (void)hipEventRecord(e1, c->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(nullptr, HGS_ERR_DEVICE, "hgs_autotune: timing failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = (double)ms / (reps * nsub);
+        if (ms_per_substep) ms_per_substep[t - 1] = per;
+        if (best_ms < 0.0 || per < best_ms) {
+            best_ms = per;
+            best = t;
+        }
+    }
+    if (st != HGS_OK && c) g_err = c->err;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hgs_destroy(c);
+    if (st != HGS_OK) return st;
+    *best_tblock = best;
+    if (cache && *cache) tune_cache_store(cache, key, best);
+    return HGS_OK;
+}

@@ -88,6 +88,7 @@ _SIGS = {
     "hgs_nn_restrict2": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
     "hgs_nn_prolong2": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
     "hgs_nn_last_error": (_cp, []),
+    "hgs_autotune": (_i32, [_CFG, _vp, _dbl, _dbl, _i32, _vp, _sz, ctypes.POINTER(_i32), _dp]),
     "hgs_destroy": (_i32, [_vp]),
     "hgs_status_str": (_cp, [_i32]),
     "hgs_last_error": (_cp, [_vp]),
@@ -297,6 +298,26 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32", lmax: int = 4,
+             x0=(-1.0, -1.0, -1.0), dx=None, eta: float = 0.0, device="cuda", stream=None):
+    """Fastest fused depth for hydro steps of nsub substeps on this grid (the
+    library times every depth on a temporary workspace).  Returns
+    (best_tblock, [ms per substep for depth 1..TMAX] or None when cached)."""
+    import torch
+
+    dev = torch.device(device)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    cfg = make_config(shape, x0, dx, 1.0, (0.0, 0.0, 0.0), lmax, "multipole", storage, 0, eta, st.cuda_stream)
+    nb = workspace_bytes(cfg)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    best = _i32(0)
+    ms = (ctypes.c_double * TMAX)()
+    _check(_lib.hgs_autotune(ctypes.byref(cfg), rho.data_ptr(), float(c_g), float(dt), int(nsub), ws.data_ptr(), nb,
+                             ctypes.byref(best), ms))
+    times = list(ms)
+    return int(best.value), (None if times[0] < 0 else times)
 
 
 class Batch:

@@ -1,0 +1,269 @@
+"""Learned warm start for the hyperbolic solver (orchestration only: every
+array operation runs in libhgs.so kernels through the hgs binding).
+
+The paper starts its runs from a Poisson solution or an interpolated exact one
+(Sec. 2).  Here a start for (phi, dphi/dt) on a fine grid is predicted instead:
+
+  1. rho (fine, n^3) is restricted to n/2 and n/4 (2x2x2 means);
+  2. a damped solve of the wave equation on the n/4 grid (multipole boundary,
+     critical damping) gives a coarse potential, prolonged to n/2 -- the global
+     cue a local network cannot build by itself;
+  3. a 4-layer 3x3x3 convolution network (16 channels, tanh, bf16 weights and
+     activations, FP32 accumulation) maps (rho, coarse phi) at n/2 to a
+     correction of phi and to dphi/dt, in units scaled by max(rho) because phi
+     is linear in rho;
+  4. the n/2 prediction is prolonged to n and handed to hgs_set_state.
+
+The zero start stays the fallback: if the warm start's residual is not below
+the zero start's, the solver starts from zero.  Steps to a residual tolerance
+count fine substeps; the coarse solve costs (n/4)^3 / n^3 of a fine substep
+per coarse substep and is reported in fine-step equivalents.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hgs
+
+NC = hgs.NN_CHANNELS
+N_LAYERS = 4
+IN_CH = 2   # rho, coarse phi
+OUT_CH = 2  # phi correction, dphi/dt
+
+
+def lambda_min(n: int, dx: float) -> float:
+    """Slowest Dirichlet mode of the 7-point Laplacian on an n^3 grid."""
+    return 3.0 * (4.0 / dx ** 2) * math.sin(math.pi / (2.0 * (n + 1))) ** 2
+
+
+def eta_critical(n: int, dx: float, c: float = 1.0) -> float:
+    return 2.0 * c * math.sqrt(lambda_min(n, dx))
+
+
+@dataclass
+class Net:
+    """Parameters: FP32 masters (w: (27,16,16), b: (16,)) per layer, bfloat16
+    copies of the weights, Adam moments."""
+
+    device: object
+    w: list = field(default_factory=list)
+    b: list = field(default_factory=list)
+    w16: list = field(default_factory=list)
+    mw: list = field(default_factory=list)
+    vw: list = field(default_factory=list)
+    mb: list = field(default_factory=list)
+    vb: list = field(default_factory=list)
+    t: int = 0
+    out_scale: float = 1.0
+
+    @staticmethod
+    def create(device, seed: int = 0) -> "Net":
+        import torch
+
+        net = Net(device)
+        g = torch.Generator().manual_seed(seed)
+        for layer in range(N_LAYERS):
+            cin = IN_CH if layer == 0 else NC
+            cout = OUT_CH if layer == N_LAYERS - 1 else NC
+            w = torch.zeros((27, NC, NC), dtype=torch.float32)
+            std = math.sqrt(1.0 / (27 * cin))
+            w[:, :cout, :cin] = torch.randn((27, cout, cin), generator=g) * std
+            if layer == N_LAYERS - 1:
+                w *= 0.1
+            net.w.append(w.to(device))
+            net.b.append(torch.zeros(NC, dtype=torch.float32, device=device))
+            net.w16.append(net.w[-1].to(torch.bfloat16))
+            for lst in (net.mw, net.vw):
+                lst.append(torch.zeros_like(net.w[-1]))
+            for lst in (net.mb, net.vb):
+                lst.append(torch.zeros_like(net.b[-1]))
+        return net
+
+    def state_dict(self) -> dict:
+        d = {"out_scale": np.array(self.out_scale)}
+        for i in range(N_LAYERS):
+            d[f"w{i}"] = self.w[i].cpu().numpy()
+            d[f"b{i}"] = self.b[i].cpu().numpy()
+        return d
+
+    def load_state_dict(self, d: dict) -> None:
+        import torch
+
+        self.out_scale = float(d["out_scale"])
+        for i in range(N_LAYERS):
+            self.w[i] = torch.from_numpy(np.asarray(d[f"w{i}"], dtype=np.float32)).to(self.device)
+            self.b[i] = torch.from_numpy(np.asarray(d[f"b{i}"], dtype=np.float32)).to(self.device)
+            self.w16[i] = self.w[i].to(torch.bfloat16)
+
+    def save(self, path: str) -> None:
+        np.savez(path, **self.state_dict())
+
+    @staticmethod
+    def load(path: str, device) -> "Net":
+        net = Net.create(device)
+        with np.load(path, allow_pickle=False) as d:
+            net.load_state_dict({k: d[k] for k in d.files})
+        return net
+
+    # -- forward / backward on packed inputs x: (B, Z, Y, X, 16) bf16
+    def forward(self, x):
+        import torch
+
+        acts = [x]
+        for i in range(N_LAYERS):
+            last = i == N_LAYERS - 1
+            out = torch.empty(x.shape, dtype=torch.float32 if last else torch.bfloat16, device=x.device)
+            hgs.nn_conv3d(acts[-1], self.w16[i], self.b[i], out, hgs.NN_F32 if last else hgs.NN_TANH_BF16)
+            acts.append(out)
+        return acts
+
+    def backward(self, acts, g_out, ws=None):
+        """g_out: bf16 gradient of the loss w.r.t. the last layer's output.
+        Returns [(dw, db)] per layer."""
+        import torch
+
+        grads = [None] * N_LAYERS
+        g = g_out
+        wt = torch.empty_like(self.w16[0])
+        for i in range(N_LAYERS - 1, -1, -1):
+            dw = torch.empty((27, NC, NC), dtype=torch.float32, device=g.device)
+            db = torch.empty(NC, dtype=torch.float32, device=g.device)
+            ws = hgs.nn_wgrad(acts[i], g, dw, db, ws)
+            grads[i] = (dw, db)
+            if i > 0:
+                hgs.nn_flip_weights(self.w16[i], wt)
+                gn = torch.empty(g.shape, dtype=torch.bfloat16, device=g.device)
+                hgs.nn_conv3d(g, wt, None, gn, hgs.NN_DTANH_BF16, aux=acts[i])
+                g = gn
+        return grads, ws
+
+    def adam_step(self, grads, lr: float):
+        self.t += 1
+        for i, (dw, db) in enumerate(grads):
+            hgs.nn_adam(self.w[i], self.mw[i], self.vw[i], dw, self.w16[i], lr, self.t)
+            hgs.nn_adam(self.b[i], self.mb[i], self.vb[i], db, None, lr, self.t)
+
+
+class Features:
+    """Coarse cue and packed network inputs for a set of fine densities."""
+
+    def __init__(self, n: int, device, coarse_steps: int = 200, lmax: int = 4):
+        self.n, self.device, self.coarse_steps, self.lmax = n, device, coarse_steps, lmax
+        self.nh, self.nq = n // 2, n // 4
+
+    def restrict(self, rho):
+        """rho: (B, n, n, n) fp32 -> (rho at n/2, rho at n/4)."""
+        import torch
+
+        B = rho.shape[0]
+        r2 = torch.empty((B, self.nh, self.nh, self.nh), dtype=rho.dtype, device=rho.device)
+        hgs.nn_restrict2(rho, r2)
+        r4 = torch.empty((B, self.nq, self.nq, self.nq), dtype=rho.dtype, device=rho.device)
+        hgs.nn_restrict2(r2, r4)
+        return r2, r4
+
+    def coarse_phi(self, r4):
+        """Damped solves on the n/4 grids (one batch), prolonged to n/2."""
+        import torch
+
+        B, m = r4.shape[0], self.nq
+        dx = 2.0 / m
+        b = hgs.Batch([m] * B, storage="f32", lmax=self.lmax, eta=eta_critical(m, dx), device=self.device)
+        rhos = [r4[i].contiguous() for i in range(B)]
+        b.step(rhos, 1.0, 0.4 * dx, self.coarse_steps)
+        phi4 = torch.stack([g.potential(with_phidot=False)[0] for g in b.grids])
+        phi2 = torch.empty((B, self.nh, self.nh, self.nh), dtype=torch.float32, device=r4.device)
+        hgs.nn_prolong2(phi4, phi2)
+        b.close()
+        return phi2
+
+    @property
+    def coarse_cost_fine_steps(self) -> float:
+        return self.coarse_steps * (self.nq / self.n) ** 3
+
+    def inputs(self, rho):
+        """Planar network inputs (B, 2, n/2^3) fp32, the coarse phi at n/2 and the
+        per-sample scale max(rho)."""
+        import torch
+
+        r2, r4 = self.restrict(rho)
+        phi2 = self.coarse_phi(r4)
+        scale = rho.reshape(rho.shape[0], -1).amax(dim=1).clamp_min(1e-30)
+        s = scale.view(-1, 1, 1, 1)
+        planar = torch.stack([r2 / s, phi2 / s], dim=1).contiguous()
+        return planar, phi2, scale
+
+
+def pack(planar):
+    import torch
+
+    B = planar.shape[0]
+    x = torch.empty((B,) + tuple(planar.shape[2:]) + (NC,), dtype=torch.bfloat16, device=planar.device)
+    hgs.nn_pack(planar, x)
+    return x
+
+
+def predict_fine(net: Net, planar, phi2, scale, n: int):
+    """Fine-grid start (phi, phidot) (B, n, n, n) fp32 from the network."""
+    import torch
+
+    B = planar.shape[0]
+    x = pack(planar)
+    out = net.forward(x)[-1]
+    pl = torch.empty((B, OUT_CH) + tuple(planar.shape[2:]), dtype=torch.float32, device=planar.device)
+    hgs.nn_unpack(out, OUT_CH, pl)
+    s = scale.view(-1, 1, 1, 1) / net.out_scale
+    phi2 = (phi2 + pl[:, 0] * s).contiguous()
+    pd2 = (pl[:, 1] * s).contiguous()
+    phi = torch.empty((B, n, n, n), dtype=torch.float32, device=planar.device)
+    pd = torch.empty_like(phi)
+    hgs.nn_prolong2(phi2, phi)
+    hgs.nn_prolong2(pd2, pd)
+    return phi, pd
+
+
+def converged_phi(rhos, n: int, device, steps: int = 1500, storage: str = "f64", lmax: int = 4):
+    """Potentials of the damped solver run to convergence (the training targets),
+    for a list of (n, n, n) densities; one batch of grids."""
+    import torch
+
+    dx = 2.0 / n
+    dt_ = torch.float64 if storage == "f64" else torch.float32
+    b = hgs.Batch([n] * len(rhos), storage=storage, lmax=lmax, eta=eta_critical(n, dx), device=device)
+    b.step([r.to(dt_).contiguous() for r in rhos], 1.0, 0.4 * dx, steps)
+    out = [g.potential(with_phidot=False)[0] for g in b.grids]
+    res = [g.residual(r.to(dt_).contiguous())[0] for g, r in zip(b.grids, rhos)]
+    b.close()
+    return out, res
+
+
+def steps_to_tolerance(rho, n: int, tol: float, start=None, max_steps: int = 4000, check: int = 4,
+                       storage: str = "f32", lmax: int = 4, device="cuda"):
+    """Substeps of the damped fine solver until R_b < tol, from zero or from
+    start = (phi, phidot).  Returns (steps, R_b at start, R_b at end)."""
+    import torch
+
+    dx = 2.0 / n
+    dt = 0.4 * dx
+    s = hgs.Solver(n, storage=storage, lmax=lmax, eta=eta_critical(n, dx), device=device)
+    dtype = s.dtype
+    r = rho.to(dtype).contiguous()
+    # one step of zero length is not allowed; set the ghosts with a first step of
+    # `check` substeps from the chosen start and count those substeps
+    if start is not None:
+        s.set_state(start[0].to(dtype).contiguous(), start[1].to(dtype).contiguous(), dt)
+    r0 = None
+    steps = 0
+    while steps < max_steps:
+        s.step(r, 1.0, dt, check)
+        steps += check
+        rb = s.residual(r)[0]
+        if r0 is None:
+            r0 = rb
+        if rb < tol:
+            break
+    s.close()
+    return steps, r0, rb

@@ -445,3 +445,21 @@ def test_batch_rejects_bad_input(gpu_lib):
     with pytest.raises(gpu_lib.HGSError) as ei:
         b.step(rhos, 1.0, [0.4 * 0.25, 0.9 * 2 / 12], 3)  # CFL violated on grid 1
     assert ei.value.status == gpu_lib.HGS_ERR_CFL
+
+
+# ------------------------------------------------------------------ autotuner
+
+def test_autotune_and_cache(gpu_lib, tmp_path, monkeypatch):
+    shape = (48, 40, 64)
+    g = grid_of(shape)
+    rho = to_dev(dens(shape, 3, "f32"))
+    monkeypatch.delenv("HGS_TUNE_CACHE", raising=False)
+    best, times = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
+    assert 1 <= best <= gpu_lib.TMAX and times is not None and len(times) == gpu_lib.TMAX
+    assert all(t > 0 for t in times) and times[best - 1] == min(times)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HGS_TUNE_CACHE", str(cache))
+    b1, t1 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
+    assert t1 is not None and cache.exists()
+    b2, t2 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
+    assert b2 == b1 and t2 is None  # served from the cache

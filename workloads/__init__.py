@@ -126,3 +126,10 @@ def batch_spec(seed: int = 2, count: int = 64, sizes=tuple(range(32, 161, 16)),
     k = rng.integers(kmin, kmax + 1, count)
     return BatchSpec(tuple(int(v) for v in n), tuple(int(v) for v in k),
                      tuple(seed_base + g for g in range(count)))
+
+
+def warmstart_blobs(seed: int) -> Blobs:
+    """Density of the warm-start study: K in {4..12} blobs, K drawn from its own
+    seeded stream, then the blob recipe above with the sample's seed."""
+    k = int(np.random.default_rng(seed + 7_000_000).integers(4, 13))
+    return blob_params(seed, k)
