@@ -25,6 +25,17 @@ arXiv:1602.05700), and what pins it (tests/test_oracle_pins.py):
   form.  Pinned by: the discrete Gauss law (telescoping flux), R_b = 1 at a
   zero state, the DST-I solution giving round-off residuals, second-order
   convergence toward the closed-form Gaussian potential.
+* ``orc_substeps_local`` / ``orc_local_ghosts`` / ``orc_residual_local`` --
+  local outer boundaries whose ghosts follow the interior every substep: the
+  Robin condition the paper uses by default ("equivalent to assuming monopole
+  gravity", Sec. 4) read as r_g phi_g = r_i phi_i; its radiative form
+  d(r phi)/dt + c d(r phi)/dr = 0 (box scheme); periodic with the domain-mean
+  density subtracted from the source (Sec. 4).  Pinned by
+  (tests/test_oracle_bc.py): exactness on -G M / r, a sparse direct solve of
+  the Robin linear system (steady state of both Robin and outgoing), an FFT
+  solve with the 7-point symbol (periodic), a free pulse leaving through the
+  outgoing boundary but not through zero-Dirichlet or static Robin ones, and
+  relaxation of a zero start without damping through the outgoing boundary.
 * ``orc_gradient`` -- g = -grad phi by central differences (the paper is silent
   on the discretisation).  Pinned by exactness on quadratics and second-order
   convergence on the Gaussian.

@@ -46,10 +46,14 @@ def lib():
             L.orc_substeps.argtypes = [i, i, i, d, _dp, _dp, _dp, d, d, d, d, i, i]
             L.orc_gradient.argtypes = [i, i, i, d, _dp, _dp, _dp, _dp]
             L.orc_residual.argtypes = [i, i, i, d, _dp, _dp, d, _dp]
+            L.orc_substeps_local.argtypes = [i, i, i, d, d, d, d, _dp, i, _dp, _dp, _dp, d, d, d, d, d, i, i]
+            L.orc_local_ghosts.argtypes = [i, i, i, d, d, d, d, _dp, i, _dp, i]
+            L.orc_residual_local.argtypes = [i, i, i, d, _dp, _dp, d, d, _dp]
             L.orc_max_threads.restype = ctypes.c_int
             L.orc_max_threads.argtypes = []
             for f in ("orc_moments", "orc_boundary", "orc_laplacian", "orc_substeps",
-                      "orc_gradient", "orc_residual"):
+                      "orc_gradient", "orc_residual", "orc_substeps_local", "orc_local_ghosts",
+                      "orc_residual_local"):
                 getattr(L, f).restype = None
             _lib = L
     return _lib
@@ -160,6 +164,36 @@ def substeps(g: Grid, Pn: np.ndarray, Pnm1: np.ndarray, rho: np.ndarray, c: floa
     lib().orc_substeps(g.nx, g.ny, g.nz, g.dx, _p(Pn), _p(Pnm1), _p(rho), c, dt, eta, G, nsub, int(f32))
 
 
+# local outer boundaries: the ghost layer follows the interior every substep
+LOCAL_BC = {"robin": 2, "outgoing": 3, "periodic": 4}
+
+
+def substeps_local(g: Grid, bc: str, Pn: np.ndarray, Pnm1: np.ndarray, rho: np.ndarray, c: float, dt: float,
+                   eta: float, G: float, nsub: int, origin=(0.0, 0.0, 0.0), rbar: float = 0.0,
+                   f32: bool = False) -> None:
+    """Advance (Pn, Pnm1) by nsub substeps with a local boundary, in place.
+    rbar is subtracted from rho in the source (the domain mean for periodic)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    lib().orc_substeps_local(g.nx, g.ny, g.nz, g.x0, g.y0, g.z0, g.dx, _p(o), LOCAL_BC[bc], _p(Pn), _p(Pnm1),
+                             _p(rho), rbar, c, dt, eta, G, nsub, int(f32))
+
+
+def local_ghosts(g: Grid, bc: str, P: np.ndarray, origin=(0.0, 0.0, 0.0), f32: bool = False) -> None:
+    """Steady form of a local rule on the ghosts of P (Robin for robin and
+    outgoing, the wrap for periodic), in place."""
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    lib().orc_local_ghosts(g.nx, g.ny, g.nz, g.x0, g.y0, g.z0, g.dx, _p(o), LOCAL_BC[bc], _p(P), int(f32))
+
+
+def residual_local(g: Grid, P: np.ndarray, rho: np.ndarray, G: float, rbar: float = 0.0) -> np.ndarray:
+    """[R_b (= R_f), R_f, ||phi||, nonfinite] with b = s = 4 pi G (rho - rbar)."""
+    out = np.zeros(4)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    lib().orc_residual_local(g.nx, g.ny, g.nz, g.dx, _p(P), _p(rho), G, rbar, _p(out))
+    return out
+
+
 def gradient(g: Grid, P: np.ndarray):
     gx, gy, gz = np.zeros(g.shape), np.zeros(g.shape), np.zeros(g.shape)
     lib().orc_gradient(g.nx, g.ny, g.nz, g.dx, _p(P), _p(gx), _p(gy), _p(gz))
@@ -190,7 +224,7 @@ class Oracle:
 
     def __init__(self, g: Grid, G: float = 1.0, lmax: int = 4, origin=(0.0, 0.0, 0.0), eta: float = 0.0,
                  bc: str = "multipole", storage: str = "f64"):
-        assert bc in ("multipole", "user")
+        assert bc in ("multipole", "user") or bc in LOCAL_BC
         assert storage in ("f64", "f32")
         self.g, self.G, self.lmax, self.origin, self.eta, self.bc = g, G, lmax, origin, eta, bc
         self.f32 = storage == "f32"
@@ -218,8 +252,16 @@ class Oracle:
             # keep the time derivative (phi^n - phi^{n-1}) / dt when the step changes
             In, Inm1 = interior(self.Pn), interior(self.Pnm1)
             Inm1[...] = self._store(In - (dt / self.dt_prev) * (In - Inm1))
-        substeps(self.g, self.Pn, self.Pnm1, rho, c, dt, self.eta, self.G, nsub, self.f32)
+        if self.bc in LOCAL_BC:
+            substeps_local(self.g, self.bc, self.Pn, self.Pnm1, rho, c, dt, self.eta, self.G, nsub, self.origin,
+                           self.rbar(rho), self.f32)
+        else:
+            substeps(self.g, self.Pn, self.Pnm1, rho, c, dt, self.eta, self.G, nsub, self.f32)
         self.dt_prev = dt
+
+    def rbar(self, rho) -> float:
+        """Density subtracted from the source: the domain mean when periodic."""
+        return float(np.mean(np.asarray(rho, dtype=np.float64))) if self.bc == "periodic" else 0.0
 
     def potential(self):
         phi = interior(self.Pn).copy()
@@ -236,7 +278,12 @@ class Oracle:
         interior(self.Pn)[...] = phi
         pd = np.zeros(self.g.shape) if phidot is None else self._store(phidot)
         interior(self.Pnm1)[...] = self._store(phi - dt * pd)
+        if self.bc in LOCAL_BC:
+            local_ghosts(self.g, self.bc, self.Pn, self.origin, self.f32)
         self.dt_prev = dt
 
     def residual(self, rho) -> np.ndarray:
-        return residual(self.g, self.Pn, np.asarray(rho, dtype=np.float64), self.G)
+        rho = np.asarray(rho, dtype=np.float64)
+        if self.bc in LOCAL_BC:
+            return residual_local(self.g, self.Pn, rho, self.G, self.rbar(rho))
+        return residual(self.g, self.Pn, rho, self.G)

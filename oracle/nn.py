@@ -15,6 +15,10 @@ plain definition written out in NumPy, in FP64:
   and 1/4 per axis; at a face the missing coarse neighbour is extrapolated
   linearly, giving 5/4 and -1/4);
 * Adam (Kingma & Ba) with bias correction;
+* a training loss that adds to the mean-squared error the squared 7-point
+  Laplacian (zero outside, index units) of one channel's error, and its
+  gradient -- the residual of the predicted potential is what sets the
+  solver's steps from a warm start, and it weighs fine-scale error heavily;
 * bfloat16 round-to-nearest-even (for feeding the oracle the same rounded
   values as the device).
 """
@@ -119,6 +123,27 @@ def adam(p, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def lap7(e: np.ndarray) -> np.ndarray:
+    """7-point Laplacian in index units over the last three axes, zero outside:
+    sum of the six neighbours minus 6 times the centre."""
+    p = np.pad(e, [(0, 0)] * (e.ndim - 3) + [(1, 1)] * 3)
+    c = p[..., 1:-1, 1:-1, 1:-1]
+    return (p[..., :-2, 1:-1, 1:-1] + p[..., 2:, 1:-1, 1:-1] + p[..., 1:-1, :-2, 1:-1]
+            + p[..., 1:-1, 2:, 1:-1] + p[..., 1:-1, 1:-1, :-2] + p[..., 1:-1, 1:-1, 2:] - 6.0 * c)
+
+
+def lap_mse(out: np.ndarray, target: np.ndarray, ch: int, w: float):
+    """out, target: (B, C, Z, Y, X).  loss = (sum e^2 + w sum (lap7 e_ch)^2) / e.size
+    with e = out - target; returns (loss, d loss / d out)."""
+    e = out - target
+    r = lap7(e[:, ch])
+    n = e.size
+    loss = (np.sum(e * e) + w * np.sum(r * r)) / n
+    g = 2.0 * e / n
+    g[:, ch] += 2.0 * w * lap7(r) / n  # lap7 is symmetric (zero padding)
+    return loss, g
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:

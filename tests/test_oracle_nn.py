@@ -126,3 +126,28 @@ def test_bf16_round():
     assert r[2] == 1.0 + 2 ** -6
     assert r[3] == -2.5
     assert abs(r[4] - 3.140625) < 1e-12
+
+
+def test_lap7_and_lap_mse_gradient():
+    # lap7 of a quadratic in the interior is its constant Laplacian (index units)
+    z, y, x = np.meshgrid(np.arange(5.0), np.arange(6.0), np.arange(7.0), indexing="ij")
+    q = (x ** 2 + 2 * y ** 2 - 0.5 * z ** 2)[None]
+    assert np.allclose(nn.lap7(q)[0, 1:-1, 1:-1, 1:-1], 2 + 4 - 1, rtol=0, atol=1e-12)
+    # at a corner the zero padding drops the three outside neighbours
+    e = np.zeros((1, 3, 3, 3))
+    e[0, 0, 0, 0] = 1.0
+    assert nn.lap7(e)[0, 0, 0, 0] == -6.0 and nn.lap7(e)[0, 1, 0, 0] == 1.0
+    # gradient by central differences
+    rng = np.random.default_rng(11)
+    out = rng.standard_normal((2, 2, 4, 3, 5))
+    tgt = rng.standard_normal((2, 2, 4, 3, 5))
+    loss, g = nn.lap_mse(out, tgt, 0, 0.7)
+    h = 1e-6
+    for _ in range(16):
+        idx = tuple(rng.integers(0, s) for s in out.shape)
+        d = np.zeros_like(out)
+        d[idx] = h
+        fd = (nn.lap_mse(out + d, tgt, 0, 0.7)[0] - nn.lap_mse(out - d, tgt, 0, 0.7)[0]) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-9)
+    # w = 0 is the plain mean-squared error
+    assert nn.lap_mse(out, tgt, 0, 0.0)[0] == pytest.approx(np.mean((out - tgt) ** 2), rel=1e-14)
