@@ -65,7 +65,24 @@ typedef enum { HGS_F64 = 0, HGS_F32 = 1 } hgs_dtype;
 
 typedef enum {
     HGS_BC_MULTIPOLE = 0, /* Dirichlet ghosts from multipole moments of rho (Sec. 2, Sec. 4) */
-    HGS_BC_USER = 1       /* Dirichlet ghosts set by hgs_set_boundary and kept */
+    HGS_BC_USER = 1,      /* Dirichlet ghosts set by hgs_set_boundary and kept */
+    /* Local boundaries: after every substep each face ghost g is set from the
+     * interior cell i next to it (r measured from cfg.origin, which must lie
+     * strictly inside the grid).  They run one substep per stencil launch
+     * (tblock does not apply) and are not available in batches. */
+    HGS_BC_ROBIN = 2,     /* the paper's default outer boundary, a Robin condition amounting to
+                             monopole gravity (Sec. 2, Sec. 4): r_g phi_g = r_i phi_i, i.e.
+                             d(r phi)/dr = 0; exact for -G M / r */
+    HGS_BC_OUTGOING = 3,  /* its radiative form d(r phi)/dt + c_g d(r phi)/dr = 0, so that errors
+                             leave through the boundary (Sec. 4); box scheme on u = r phi at the
+                             ghost/neighbour midpoint x_f, d/dr = d/dn / cos(theta),
+                             alpha = c_g dt / (dx cos(theta)):
+                               u_g' = [(1-alpha) u_g + (1+alpha) u_i - (1-alpha) u_i'] / (1+alpha)
+                             (primes: the new level).  Steady state = Robin's.  Lets a zero
+                             start relax with eta = 0. */
+    HGS_BC_PERIODIC = 4   /* ghost = interior cell at the opposite face; the source is
+                             4 pi G (rho - mean rho) (Sec. 4), the mean taken in FP64 each
+                             hgs_step; a zero start keeps mean(phi) = 0 */
 } hgs_bc;
 
 /* Largest temporal-blocking depth (substeps fused per launch). */
@@ -127,11 +144,16 @@ hgs_status hgs_accel(hgs_ctx* ctx, void* gx, void* gy, void* gz);
 
 /* Set the state from a potential and its time derivative: phi^n = phi,
  * phi^{n-1} = phi - dt * phidot (phidot NULL means 0).  dt > 0 becomes the
- * "previous step" for the dt-rescaling rule of hgs_step. */
+ * "previous step" for the dt-rescaling rule of hgs_step.  With a local
+ * boundary the ghosts of both levels are then set from their interiors by the
+ * steady rule (Robin's relation for ROBIN and OUTGOING, the wrap for PERIODIC). */
 hgs_status hgs_set_state(hgs_ctx* ctx, const void* phi, const void* phidot, double dt);
 
-/* bc = USER only (else HGS_ERR_STATE): set the ghost faces (device, storage
- * dtype, face layout above).  They stay until the next call. */
+/* bc = USER (else HGS_ERR_STATE, except OUTGOING): set the ghost faces
+ * (device, storage dtype, face layout above); they stay until the next call.
+ * bc = OUTGOING: the ghosts carry state (u_g of the box scheme); this call
+ * restores them, e.g. after hgs_load_raw, which otherwise rebuilds every local
+ * boundary's ghosts from the interior by the steady rule. */
 hgs_status hgs_set_boundary(hgs_ctx* ctx, const void* ghosts);
 
 /* Copy the current ghost faces into a device buffer (face layout above). */
@@ -148,12 +170,43 @@ hgs_status hgs_moments(hgs_ctx* ctx, double* q_host);
  *   out[0] = R_b = ||L_h phi - s|| / ||b||, b = s - (adjacent ghosts)/dx^2
  *            (the textbook relative residual of the interior linear system;
  *            1 at phi = 0),
- *   out[1] = R_f = ||L_h phi - s|| / ||s||,  s = 4 pi G rho,
+ *            With a local boundary the ghosts are images of interior unknowns,
+ *            so b = s and R_b = R_f,
+ *   out[1] = R_f = ||L_h phi - s|| / ||s||,  s = 4 pi G rho (PERIODIC:
+ *            4 pi G (rho - mean rho)),
  *   out[2] = ||phi|| over the interior,
  *   out[3] = 1 if phi or rho holds a NaN/Inf (status HGS_ERR_NONFINITE), else 0.
  * 2-norms over interior cells, FP64.  A zero denominator gives 0 for a zero
  * numerator and +inf otherwise. */
 hgs_status hgs_residual(hgs_ctx* ctx, const void* rho, double out[4]);
+
+/* ---- Coupling to a hydrodynamics code ---------------------------------------
+ * The paper sets the propagation speed from the flow, c_g = k_g (c_s + |v|)
+ * (Eq. 3, k_g > 1), and advances gravity on its own timeline: k_g wave
+ * substeps per hydrodynamical step with the same Courant number (Sec. 2).
+ * Read here with c_s + |v| maximised over the grid, since c_g is one speed. */
+
+/* Synchronises.  *vmax = max over cells of c_s + |v| (FP64); cs: device
+ * (nz,ny,nx) in the storage dtype; vx, vy, vz likewise, each nullable (0).
+ * HGS_ERR_NONFINITE if any value is NaN/Inf. */
+hgs_status hgs_max_signal_speed(hgs_ctx* ctx, const void* cs, const void* vx, const void* vy, const void* vz,
+                                double* vmax);
+
+/* Synchronises (reads the signal speed back).  One hydrodynamical step of the
+ * coupled scheme: vmax = max(c_s + |v|), dt_hydro = courant_hydro dx / vmax,
+ * c_g = k_g vmax, nsub = ceil(k_g courant_hydro / courant_grav) (the smallest
+ * count with c_g (dt_hydro / nsub) / dx <= courant_grav; = ceil(k_g) for equal
+ * Courant numbers), then hgs_step(rho, c_g, dt_hydro / nsub, nsub).  Outputs
+ * dt_hydro, nsub and c_g.  Errors: HGS_ERR_ARG for k_g < 1, courant_hydro <= 0,
+ * courant_grav outside (0, 1/sqrt(3)], a zero signal speed or more than 1e6
+ * substeps; those of hgs_max_signal_speed and hgs_step. */
+hgs_status hgs_hydro_step(hgs_ctx* ctx, const void* rho, const void* cs, const void* vx, const void* vy,
+                          const void* vz, double k_g, double courant_hydro, double courant_grav, double* dt_hydro,
+                          int32_t* nsub, double* c_g);
+
+/* Synchronises.  Gravitational energy W = 1/2 sum_cells rho phi dx^3 of the
+ * current potential (FP64), rho device (nz,ny,nx) in the storage dtype. */
+hgs_status hgs_energy(hgs_ctx* ctx, const void* rho, double* w);
 
 /* Bitwise copy of the raw two-level state (phi^n, phi^{n-1} interiors, device
  * (nz,ny,nx) buffers) and the previous step size, for checkpoint/resume. */
@@ -242,6 +295,16 @@ hgs_status hgs_nn_unpack(const float* in, int32_t B, int32_t C, int64_t nvox, fl
 #define HGS_NN_MSE_PARTIALS 1024
 hgs_status hgs_nn_mse(const float* out, const float* target, int32_t B, int32_t C, int64_t nvox, uint16_t* grad,
                       double* loss_dev, double* partials, void* stream);
+/* The same with a Laplacian term on channel ch: with e = out - target and L
+ * the 7-point Laplacian in index units (zero outside the (nz, ny, nx) box),
+ *   loss = sum_c,v e_c^2 + w sum_v (L e_ch)^2      (*loss_dev, device double)
+ *   grad = (2 e + [c == ch] 2 w L(L e_ch)) / (B C nvox)   (bf16 channels-last).
+ * The residual of a predicted potential, which sets the solver's steps from a
+ * warm start, weighs fine-scale error with the Laplacian.  scratch: device
+ * FP32, B*nz*ny*nx elements; partials: HGS_NN_MSE_PARTIALS doubles. */
+hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32_t C, int32_t nz, int32_t ny,
+                         int32_t nx, int32_t ch, float w, float* scratch, uint16_t* grad, double* loss_dev,
+                         double* partials, void* stream);
 /* Adam with bias correction (step t >= 1) on FP32 master parameters; p16
  * (nullable) receives their bfloat16 copy. */
 hgs_status hgs_nn_adam(float* p, float* m, float* v, const float* g, uint16_t* p16, int32_t n, float lr, float b1,

@@ -194,6 +194,11 @@ def residual_local(g: Grid, P: np.ndarray, rho: np.ndarray, G: float, rbar: floa
     return out
 
 
+def energy(g: Grid, rho: np.ndarray, phi: np.ndarray) -> float:
+    """Gravitational energy W = 1/2 sum_cells rho phi dx^3 (phi compact)."""
+    return float(0.5 * np.sum(np.asarray(rho, dtype=np.float64) * np.asarray(phi, dtype=np.float64)) * g.dx ** 3)
+
+
 def gradient(g: Grid, P: np.ndarray):
     gx, gy, gz = np.zeros(g.shape), np.zeros(g.shape), np.zeros(g.shape)
     lib().orc_gradient(g.nx, g.ny, g.nz, g.dx, _p(P), _p(gx), _p(gy), _p(gz))

@@ -21,6 +21,7 @@
 #include "k_stencil.hpp"
 #include "k_tblock.hpp"
 #include "k_batch.hpp"
+#include "k_local.hpp"
 #include <algorithm>
 #include <cstdlib>
 #include <fstream>
@@ -43,6 +44,7 @@ struct hgs_ctx {
     bool mom_vec;  // 16-byte loads along x (nx a multiple of the vector width)
     double* red_partial;
     double* red_out;
+    double* mean;  // domain-mean density (periodic boundary), device
     int red_blocks;
     double dt_prev;
     bool have_moments;
@@ -81,7 +83,7 @@ hgs_status fail(hgs_ctx* c, hgs_status s, const std::string& msg) {
 
 struct Plan {
     size_t buf_bytes;  // one padded state buffer
-    size_t mom_partial_off, mom_off, red_partial_off, red_out_off, total;
+    size_t mom_partial_off, mom_off, red_partial_off, red_out_off, mean_off, total;
     int mom_blocks, mom_zc, mom_tx, mom_ty;
     bool mom_vec;
 };
@@ -108,8 +110,8 @@ hgs_status check_config(const hgs_config* cfg, std::string& why) {
         why = "lmax must be in 0..4";
         return HGS_ERR_ARG;
     }
-    if (cfg->bc != HGS_BC_MULTIPOLE && cfg->bc != HGS_BC_USER) {
-        why = "bc must be HGS_BC_MULTIPOLE or HGS_BC_USER";
+    if (cfg->bc < HGS_BC_MULTIPOLE || cfg->bc > HGS_BC_PERIODIC) {
+        why = "bc must be one of HGS_BC_MULTIPOLE, USER, ROBIN, OUTGOING, PERIODIC";
         return HGS_ERR_ARG;
     }
     if (cfg->storage != HGS_F64 && cfg->storage != HGS_F32) {
@@ -124,9 +126,10 @@ hgs_status check_config(const hgs_config* cfg, std::string& why) {
         why = "eta must be >= 0 and finite";
         return HGS_ERR_ARG;
     }
-    if (cfg->bc == HGS_BC_MULTIPOLE) {
-        // the exterior expansion is evaluated at the ghost centres; with the
-        // centre strictly inside the grid they all lie at r >= dx/2 > 0
+    if (cfg->bc == HGS_BC_MULTIPOLE || cfg->bc == HGS_BC_ROBIN || cfg->bc == HGS_BC_OUTGOING) {
+        // the exterior expansion and the r-weighted local rules are evaluated
+        // at the ghost centres; with the centre strictly inside the grid they
+        // all lie at r >= dx/2 > 0 and every face is seen at cos(theta) > 0
         const double lo[3] = {cfg->x0, cfg->y0, cfg->z0};
         const int n[3] = {cfg->nx, cfg->ny, cfg->nz};
         for (int d = 0; d < 3; ++d)
@@ -169,6 +172,8 @@ Plan make_plan(const hgs_config* cfg) {
     off = align_up(off + (size_t)kRedBlocks * NRED * sizeof(double), kAlign);
     p.red_out_off = off;
     off = align_up(off + NRED * sizeof(double), kAlign);
+    p.mean_off = off;
+    off = align_up(off + sizeof(double), kAlign);
     p.total = off;
     return p;
 }
@@ -291,10 +296,40 @@ void run_moments_and_ghosts(hgs_ctx* c, const void* rho) {
     tm.end((double)sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz + 4.0 * sizeof(S) * (double)nf, 0.0);
 }
 
+// Boundaries whose ghosts follow the interior every substep (one substep per
+// stencil launch, then a ghost launch), as opposed to ghosts frozen over a
+// hydrodynamical step (multipole, user).
+bool local_bc(int bc) { return bc == HGS_BC_ROBIN || bc == HGS_BC_OUTGOING || bc == HGS_BC_PERIODIC; }
+
+LocalGeom local_geom(const hgs_ctx* c) {
+    return LocalGeom{c->cfg.x0, c->cfg.y0, c->cfg.z0, c->cfg.dx, c->cfg.origin[0], c->cfg.origin[1], c->cfg.origin[2]};
+}
+
+// New level's ghosts from its interior (cur = the previous level for the
+// outgoing rule; nullptr = each rule's steady form).
 template <typename S>
-void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub) {
+void run_local_ghosts(hgs_ctx* c, int nxt, int cur, double c_dt) {
+    const int maxfast = std::max(c->L.nx, c->L.ny), maxslow = std::max(c->L.ny, c->L.nz);
+    hipLaunchKernelGGL(k_local_ghosts<S>, dim3((maxfast + 255) / 256, maxslow, 6), dim3(256), 0, c->stream, c->L,
+                       local_geom(c), c->cfg.bc, B<S>(c, nxt), cur >= 0 ? (const S*)B<S>(c, cur) : nullptr, c_dt);
+}
+
+// Domain-mean density into c->mean (FP64; fixed-order partial sums).
+template <typename S>
+void run_mean(hgs_ctx* c, const void* rho) {
+    const int64_t n = (int64_t)c->cfg.nx * c->cfg.ny * c->cfg.nz;
+    const int nb = grid_for(n, 256, kRedBlocks);
+    hipLaunchKernelGGL(k_sum_partial<S>, dim3(nb), dim3(256), 0, c->stream, static_cast<const S*>(rho), n,
+                       c->red_partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c->stream, c->red_partial, nb, 1.0 / (double)n, c->mean);
+}
+
+template <typename S>
+void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, double c_dt) {
     const S* r = static_cast<const S*>(rho);
-    int T = c->tblock;
+    const bool local = local_bc(c->cfg.bc);
+    const double* rbar = c->cfg.bc == HGS_BC_PERIODIC ? c->mean : nullptr;
+    int T = local ? 1 : c->tblock;
     while (nsub > 0) {
         if (T > 1 && nsub >= T) {
             // out of place: (cur, old) -> (the other two buffers)
@@ -320,14 +355,17 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub) {
             if (use_vec<S>(c->L)) {
                 stream_dims(c->L, 64 * Vec16<S>::N, zc, tx, ty, nb);
                 hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream,
-                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty);
+                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar);
             } else {
                 stream_dims(c->L, SBX, zc, tx, ty, nb);
                 hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream,
-                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty);
+                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar);
             }
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(4.0 * sizeof(S) * cells, cells);
+            // the new level (written over phi^{n-1}) gets its ghosts from its
+            // interior and, for the outgoing rule, from phi^n
+            if (local) run_local_ghosts<S>(c, c->old, c->cur, c_dt);
             std::swap(c->cur, c->old);
             nsub -= 1;
         }
@@ -382,6 +420,10 @@ template <typename S>
 void run_set_state(hgs_ctx* c, const void* phi, const void* phidot, double dt) {
     hipLaunchKernelGGL(k_set_state<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, B<S>(c, c->cur),
                        B<S>(c, c->old), static_cast<const S*>(phi), static_cast<const S*>(phidot), dt, c->L);
+    if (local_bc(c->cfg.bc)) {
+        run_local_ghosts<S>(c, c->cur, -1, 0.0);
+        run_local_ghosts<S>(c, c->old, -1, 0.0);
+    }
 }
 
 template <typename S>
@@ -415,8 +457,14 @@ void run_residual(hgs_ctx* c, const void* rho) {
         zc = c->L.nz;
         nb = cols;
     }
+    const double* rbar = nullptr;
+    if (c->cfg.bc == HGS_BC_PERIODIC) {
+        run_mean<S>(c, rho);
+        rbar = c->mean;
+    }
     hipLaunchKernelGGL(k_residual_partial<S>, dim3(nb), dim3(64, 4), 0, c->stream, B<S>(c, c->cur),
-                       static_cast<const S*>(rho), c->L, idx2, 4.0 * M_PI * c->cfg.G, zc, tx, ty, c->red_partial);
+                       static_cast<const S*>(rho), c->L, idx2, 4.0 * M_PI * c->cfg.G, zc, tx, ty, rbar,
+                       local_bc(c->cfg.bc) ? 0 : 1, c->red_partial);
     hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, c->stream, c->red_partial, nb, c->red_out);
 }
 
@@ -434,6 +482,38 @@ void run_raw_in(hgs_ctx* c, const void* a, const void* b) {
                        static_cast<const S*>(a), c->L, B<S>(c, c->cur));
     hipLaunchKernelGGL(k_interior_in<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream,
                        static_cast<const S*>(b), c->L, B<S>(c, c->old));
+    if (local_bc(c->cfg.bc)) {
+        run_local_ghosts<S>(c, c->cur, -1, 0.0);
+        run_local_ghosts<S>(c, c->old, -1, 0.0);
+    }
+}
+
+// max over cells of c_s + |v| and a non-finite flag into red_out[0..1]
+template <typename S>
+void run_speed(hgs_ctx* c, const void* cs, const void* vx, const void* vy, const void* vz) {
+    const int64_t n = ncell(c);
+    const int nb = grid_for(n, 256, kRedBlocks);
+    hipLaunchKernelGGL(k_speed_partial<S>, dim3(nb), dim3(256), 0, c->stream, static_cast<const S*>(cs),
+                       static_cast<const S*>(vx), static_cast<const S*>(vy), static_cast<const S*>(vz), n,
+                       c->red_partial);
+    hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(64), 0, c->stream, c->red_partial, nb, c->red_out);
+}
+
+// W = 1/2 sum rho phi dx^3 into red_out[0]
+template <typename S>
+void run_energy(hgs_ctx* c, const void* rho) {
+    const int nb = grid_for(ncell(c), 256, kRedBlocks);
+    hipLaunchKernelGGL(k_dot_partial<S>, dim3(nb), dim3(256), 0, c->stream, static_cast<const S*>(rho),
+                       B<S>(c, c->cur), c->L, c->red_partial);
+    const double dv = c->cfg.dx * c->cfg.dx * c->cfg.dx;
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c->stream, c->red_partial, nb, 0.5 * dv, c->red_out);
+}
+
+hgs_status read_out(hgs_ctx* c, double* dst, int n, const char* what) {
+    hipError_t e = hipMemcpyAsync(dst, c->red_out, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, HGS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return HGS_OK;
 }
 
 // Default fused depth: four substeps per launch (the usual substeps per hydro
@@ -516,6 +596,7 @@ hgs_status hgs_init(const hgs_config* cfg, void* workspace, size_t bytes, hgs_ct
     c->mom_vec = p.mom_vec;
     c->red_partial = reinterpret_cast<double*>(w + p.red_partial_off);
     c->red_out = reinterpret_cast<double*>(w + p.red_out_off);
+    c->mean = reinterpret_cast<double*>(w + p.mean_off);
     c->red_blocks = kRedBlocks;
     c->dt_prev = 0.0;
     c->have_moments = false;
@@ -626,8 +707,9 @@ hgs_status hgs_step(hgs_ctx* ctx, const void* rho, double c_g, double dt, int32_
         DISPATCH(ctx, run_moments_and_ghosts, ctx, rho);
         ctx->have_moments = true;
     }
+    if (ctx->cfg.bc == HGS_BC_PERIODIC) DISPATCH(ctx, run_mean, ctx, rho);
     if (ctx->dt_prev > 0.0 && dt != ctx->dt_prev) DISPATCH(ctx, run_rescale, ctx, dt / ctx->dt_prev);
-    DISPATCH(ctx, run_substeps, ctx, rho, step_coef(ctx, c_g, dt), nsub);
+    DISPATCH(ctx, run_substeps, ctx, rho, step_coef(ctx, c_g, dt), nsub, c_g * dt);
     ctx->dt_prev = dt;
     return launch_check(ctx, "hgs_step");
 }
@@ -660,7 +742,8 @@ hgs_status hgs_set_state(hgs_ctx* ctx, const void* phi, const void* phidot, doub
 
 hgs_status hgs_set_boundary(hgs_ctx* ctx, const void* ghosts) {
     if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
-    if (ctx->cfg.bc != HGS_BC_USER) return fail(ctx, HGS_ERR_STATE, "hgs_set_boundary needs bc = HGS_BC_USER");
+    if (ctx->cfg.bc != HGS_BC_USER && ctx->cfg.bc != HGS_BC_OUTGOING)
+        return fail(ctx, HGS_ERR_STATE, "hgs_set_boundary needs bc = HGS_BC_USER or HGS_BC_OUTGOING");
     if (!ghosts) return fail(ctx, HGS_ERR_ARG, "ghosts is NULL");
     (void)hipGetLastError();
     DISPATCH(ctx, run_faces_in, ctx, ghosts);
@@ -725,6 +808,62 @@ hgs_status hgs_residual(hgs_ctx* ctx, const void* rho, double out[4]) {
     out[3] = r[4] > 0.0 ? 1.0 : 0.0;
     if (out[3] != 0.0) return fail(ctx, HGS_ERR_NONFINITE, "phi or rho holds a non-finite value");
     return HGS_OK;
+}
+
+hgs_status hgs_max_signal_speed(hgs_ctx* ctx, const void* cs, const void* vx, const void* vy, const void* vz,
+                                double* vmax) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!cs || !vmax) return fail(ctx, HGS_ERR_ARG, "cs and vmax must be non-NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_speed, ctx, cs, vx, vy, vz);
+    hgs_status s = launch_check(ctx, "hgs_max_signal_speed");
+    if (s != HGS_OK) return s;
+    double r[2];
+    s = read_out(ctx, r, 2, "hgs_max_signal_speed");
+    if (s != HGS_OK) return s;
+    *vmax = r[0];
+    if (r[1] != 0.0) return fail(ctx, HGS_ERR_NONFINITE, "c_s or v holds a non-finite value");
+    return HGS_OK;
+}
+
+hgs_status hgs_hydro_step(hgs_ctx* ctx, const void* rho, const void* cs, const void* vx, const void* vy,
+                          const void* vz, double k_g, double courant_hydro, double courant_grav, double* dt_hydro,
+                          int32_t* nsub, double* c_g) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!rho || !cs || !dt_hydro || !nsub || !c_g)
+        return fail(ctx, HGS_ERR_ARG, "rho, cs, dt_hydro, nsub and c_g must be non-NULL");
+    if (!(k_g >= 1.0) || !std::isfinite(k_g)) return fail(ctx, HGS_ERR_ARG, "k_g must be >= 1 and finite");
+    if (!(courant_hydro > 0.0) || !std::isfinite(courant_hydro))
+        return fail(ctx, HGS_ERR_ARG, "courant_hydro must be positive and finite");
+    if (!(courant_grav > 0.0) || courant_grav > 1.0 / std::sqrt(3.0))
+        return fail(ctx, HGS_ERR_ARG, "courant_grav must be in (0, 1/sqrt(3)]");
+    double vmax = 0.0;
+    hgs_status s = hgs_max_signal_speed(ctx, cs, vx, vy, vz, &vmax);
+    if (s != HGS_OK) return s;
+    if (!(vmax > 0.0)) return fail(ctx, HGS_ERR_ARG, "the largest signal speed c_s + |v| is zero");
+    const double dth = courant_hydro * ctx->cfg.dx / vmax;
+    const double cg = k_g * vmax;
+    // the wave step must satisfy c_g dt / dx <= courant_grav
+    const double need = k_g * courant_hydro / courant_grav;
+    if (need > 1.0e6) return fail(ctx, HGS_ERR_ARG, "more than 1e6 substeps per hydrodynamical step");
+    int n = (int)std::ceil(need * (1.0 - 1e-12));
+    if (n < 1) n = 1;
+    s = hgs_step(ctx, rho, cg, dth / n, n);
+    if (s != HGS_OK) return s;
+    *dt_hydro = dth;
+    *nsub = n;
+    *c_g = cg;
+    return HGS_OK;
+}
+
+hgs_status hgs_energy(hgs_ctx* ctx, const void* rho, double* w) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!rho || !w) return fail(ctx, HGS_ERR_ARG, "rho and w must be non-NULL");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_energy, ctx, rho);
+    hgs_status s = launch_check(ctx, "hgs_energy");
+    if (s != HGS_OK) return s;
+    return read_out(ctx, w, 1, "hgs_energy");
 }
 
 hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev) {
@@ -848,6 +987,10 @@ hgs_status batch_plan(const hgs_config* cfgs, int32_t n, BatchPlan& p, std::stri
         if (s != HGS_OK) {
             why = "grid " + std::to_string(i) + ": " + why;
             return s;
+        }
+        if (local_bc(cfgs[i].bc)) {
+            why = "grid " + std::to_string(i) + ": batched grids need a boundary frozen over the step (multipole or user)";
+            return HGS_ERR_ARG;
         }
         if (cfgs[i].storage != cfgs[0].storage || cfgs[i].stream != cfgs[0].stream ||
             cfgs[i].tblock != cfgs[0].tblock) {
@@ -1197,6 +1340,12 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
     if (!best_tblock) return fail(nullptr, HGS_ERR_ARG, "best_tblock is NULL");
     s = validate_step(nullptr, cfg, rho, c_g, dt, nsub);
     if (s != HGS_OK) return s;
+    if (local_bc(cfg->bc)) {  // one substep per launch: nothing to choose
+        *best_tblock = 1;
+        if (ms_per_substep)
+            for (int i = 0; i < HGS_TMAX; ++i) ms_per_substep[i] = -1.0;
+        return HGS_OK;
+    }
     const char* cache = std::getenv("HGS_TUNE_CACHE");
     const std::string key = tune_key(cfg, nsub);
     if (cache && *cache) {

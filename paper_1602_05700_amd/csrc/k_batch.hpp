@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64 * BY) void k_stream_batch(const GridDesc<S>* __r
         const GridDesc<S>& g = grids[wi.grid];
         const Layout L = g.L;
         const StepCoef c = g.c;
-        stream_v_tile<S, BY>(g.buf[cur], g.buf[old], g.rho, L, c, wi.tx, wi.ty, wi.k0, wi.k1);
+        stream_v_tile<S, BY>(g.buf[cur], g.buf[old], g.rho, L, c, wi.tx, wi.ty, wi.k0, wi.k1, 0.0);
     }
 }
 

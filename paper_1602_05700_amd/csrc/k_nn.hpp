@@ -243,6 +243,81 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ out, cons
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Laplacian-weighted loss.  With e = out[..., ch] - target[b][ch] and L the
+// 7-point Laplacian in index units with zero outside the box,
+//   loss = sum_c sum_v e_c^2 + w sum_v (L e_ch)^2,
+//   d loss / d out_c = 2 e_c + [c == ch] 2 w L(L e_ch)     (L is symmetric).
+// First pass: r = L e_ch into an FP32 planar scratch [B][nvox].
+__device__ __forceinline__ double lap_err(const float* __restrict__ out, const float* __restrict__ target, int C,
+                                          int ch, int nz, int ny, int nx, int64_t b, int i, int j, int k) {
+    if (i < 0 || i >= nx || j < 0 || j >= ny || k < 0 || k >= nz) return 0.0;
+    const int64_t nvox = (int64_t)nz * ny * nx;
+    const int64_t v = ((int64_t)k * ny + j) * nx + i;
+    return (double)out[(b * nvox + v) * NC + ch] - (double)target[(b * C + ch) * nvox + v];
+}
+
+__global__ __launch_bounds__(256) void k_lapres(const float* __restrict__ out, const float* __restrict__ target, int B,
+                                                int C, int ch, int nz, int ny, int nx, float* __restrict__ r) {
+    const int64_t nvox = (int64_t)nz * ny * nx, total = (int64_t)B * nvox;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t / nvox, v = t % nvox;
+        const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((int64_t)nx * ny));
+        const double nb = ((lap_err(out, target, C, ch, nz, ny, nx, b, i - 1, j, k) +
+                            lap_err(out, target, C, ch, nz, ny, nx, b, i + 1, j, k)) +
+                           (lap_err(out, target, C, ch, nz, ny, nx, b, i, j - 1, k) +
+                            lap_err(out, target, C, ch, nz, ny, nx, b, i, j + 1, k))) +
+                          (lap_err(out, target, C, ch, nz, ny, nx, b, i, j, k - 1) +
+                           lap_err(out, target, C, ch, nz, ny, nx, b, i, j, k + 1));
+        r[t] = (float)(nb - 6.0 * lap_err(out, target, C, ch, nz, ny, nx, b, i, j, k));
+    }
+}
+
+__device__ __forceinline__ double lap_at(const float* __restrict__ r, int nz, int ny, int nx, int64_t b, int i, int j,
+                                         int k) {
+    if (i < 0 || i >= nx || j < 0 || j >= ny || k < 0 || k >= nz) return 0.0;
+    return (double)r[(b * nz + k) * (int64_t)ny * nx + (int64_t)j * nx + i];
+}
+
+// Second pass: gradient (bf16 channels-last, scaled by inv_count) and block
+// partial sums of the loss.
+__global__ __launch_bounds__(256) void k_lapmse(const float* __restrict__ out, const float* __restrict__ target,
+                                                const float* __restrict__ r, int B, int C, int ch, int nz, int ny,
+                                                int nx, float w, float inv_count, uint16_t* __restrict__ grad,
+                                                double* __restrict__ partial) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    const int64_t nvox = (int64_t)nz * ny * nx, total = (int64_t)B * nvox;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t / nvox, v = t % nvox;
+        const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((int64_t)nx * ny));
+        const double rc = (double)r[t];
+        const double lr = (((lap_at(r, nz, ny, nx, b, i - 1, j, k) + lap_at(r, nz, ny, nx, b, i + 1, j, k)) +
+                            (lap_at(r, nz, ny, nx, b, i, j - 1, k) + lap_at(r, nz, ny, nx, b, i, j + 1, k))) +
+                           (lap_at(r, nz, ny, nx, b, i, j, k - 1) + lap_at(r, nz, ny, nx, b, i, j, k + 1))) -
+                          6.0 * rc;
+        acc += (double)w * rc * rc;
+        uint16_t h[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double g = 0.0;
+            if (c < C) {
+                const double d = (double)out[t * NC + c] - (double)target[(b * C + c) * nvox + v];
+                acc += d * d;
+                g = 2.0 * d;
+                if (c == ch) g += 2.0 * (double)w * lr;
+            }
+            h[c] = f2bf((float)(g * (double)inv_count));
+        }
+        uint16_t* o = grad + t * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) o[c] = h[c];
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 __global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         double s = 0.0;

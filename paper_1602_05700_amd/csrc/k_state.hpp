@@ -148,14 +148,17 @@ __global__ void k_faces_in(const S* __restrict__ src, Layout L, S* b0, S* b1, S*
 }
 
 // Residual partial sums per workgroup: [rr, bb, ss, pp, bad].
-//   r = L_h phi - s,  b = s - (adjacent ghosts)/dx^2,  s = 4 pi G rho.
+//   r = L_h phi - s,  s = 4 pi G (rho - rbar)  (rbar nullable: 0),
+//   b = s - (adjacent ghosts)/dx^2 for a fixed boundary (ghosts_in_b), else
+//   b = s: a local boundary's ghosts are images of interior unknowns.
 constexpr int NRED = 5;
 // One workgroup per (64 x 4 column tile, z chunk); each thread marches its
 // column.  Fixed-order reductions: wave butterfly, then the four waves.
 template <typename S>
 __global__ __launch_bounds__(256) void k_residual_partial(const S* __restrict__ phi, const S* __restrict__ rho,
                                                           Layout L, double idx2, double four_pi_g, int zc,
-                                                          int tiles_x, int tiles_y, double* __restrict__ partial) {
+                                                          int tiles_x, int tiles_y, const double* __restrict__ rbar,
+                                                          int ghosts_in_b, double* __restrict__ partial) {
     __shared__ double red[4][NRED];
     double acc[NRED] = {0, 0, 0, 0, 0};
     const int bid = blockIdx.x;
@@ -170,6 +173,7 @@ __global__ __launch_bounds__(256) void k_residual_partial(const S* __restrict__ 
         const int64_t sxy = (int64_t)L.nx * L.ny;
         const S* pc = phi + L.idx(i, j, k0);
         const S* pr = rho + (int64_t)k0 * sxy + (int64_t)j * L.nx + i;
+        const double rb = rbar ? *rbar : 0.0;
         for (int k = k0; k < k1; ++k) {
             const double c = (double)pc[0];
             const double xm = (double)pc[-1], xp = (double)pc[1];
@@ -183,10 +187,10 @@ __global__ __launch_bounds__(256) void k_residual_partial(const S* __restrict__ 
             if (k == 0) gb += zm;
             if (k == L.nz - 1) gb += zp;
             const double rv = (double)pr[0];
-            const double s = four_pi_g * rv;
+            const double s = four_pi_g * (rv - rb);
             const double nb = ((xm + xp) + (ym + yp)) + (zm + zp);
             const double r = (nb - 6.0 * c) * idx2 - s;
-            const double b = s - gb * idx2;
+            const double b = ghosts_in_b ? s - gb * idx2 : s;
             acc[0] += r * r;
             acc[1] += b * b;
             acc[2] += s * s;

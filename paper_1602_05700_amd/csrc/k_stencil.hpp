@@ -13,10 +13,14 @@
 
 namespace hgs {
 
+// rbar (nullable, device): density subtracted from rho in the source, the
+// domain mean on a periodic grid; rho - 0 = rho exactly, so results without it
+// are bit-identical to the fused kernels.
 template <typename S, int BX, int BY>
 __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict__ cur, S* __restrict__ old_new,
                                                             const S* __restrict__ rho, Layout L, StepCoef c,
-                                                            int zc, int tiles_x, int tiles_y) {
+                                                            int zc, int tiles_x, int tiles_y,
+                                                            const double* __restrict__ rbar) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = bid % tiles_x;
     const int ty = (bid / tiles_x) % tiles_y;
@@ -33,6 +37,7 @@ __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict_
     S* po = old_new + o0;
     const int64_t sxy = (int64_t)L.nx * L.ny;
     const S* pr = rho + (int64_t)k0 * sxy + (int64_t)j * L.nx + i;
+    const double rb = rbar ? *rbar : 0.0;
     double zm = ld(pc - plane);
     double z0 = ld(pc);
     for (int k = k0; k < k1; ++k) {
@@ -40,7 +45,7 @@ __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict_
         const double xm = ld(pc - 1), xp = ld(pc + 1);
         const double ym = ld(pc - pitch), yp = ld(pc + pitch);
         const double o = ld(po);
-        const double r = ld(pr);
+        const double r = ld(pr) - rb;
         *po = (S)leapfrog_update(c, z0, xm, xp, ym, yp, zm, zp, o, r);
         zm = z0;
         z0 = zp;
@@ -168,7 +173,7 @@ __device__ __forceinline__ VLane vlane(const Layout& L, int tx, int ty, int BY) 
 template <typename S, int BY>
 __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __restrict__ old_new,
                                               const S* __restrict__ rho, const Layout& L, const StepCoef& c, int tx,
-                                              int ty, int k0, int k1) {
+                                              int ty, int k0, int k1, double rb) {
     using V = Vec16<S>;
     using VT = typename V::T;
     constexpr int N = V::N;
@@ -200,7 +205,7 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
             const double xp = n < N - 1 ? (double)V::get(z0, n + 1) : (double)right;
             const double v = leapfrog_update(c, (double)V::get(z0, n), xm, xp, (double)V::get(ym, n),
                                              (double)V::get(yp, n), (double)V::get(zm, n), (double)V::get(zp, n),
-                                             (double)V::get(o, n), (double)V::get(r, n));
+                                             (double)V::get(o, n), (double)V::get(r, n) - rb);
             V::set(out, n, (S)v);
         }
         if (g.active) *reinterpret_cast<VT*>(po) = out;
@@ -215,13 +220,14 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
 template <typename S, int BY>
 __global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restrict__ cur, S* __restrict__ old_new,
                                                                const S* __restrict__ rho, Layout L, StepCoef c, int zc,
-                                                               int tiles_x, int tiles_y) {
+                                                               int tiles_x, int tiles_y,
+                                                               const double* __restrict__ rbar) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = bid % tiles_x;
     const int ty = (bid / tiles_x) % tiles_y;
     const int tz = bid / (tiles_x * tiles_y);
     const int k0 = tz * zc;
-    stream_v_tile<S, BY>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz));
+    stream_v_tile<S, BY>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz), rbar ? *rbar : 0.0);
 }
 
 template <typename S, int BY>

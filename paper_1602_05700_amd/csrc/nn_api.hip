@@ -119,6 +119,26 @@ hgs_status hgs_nn_mse(const float* out, const float* target, int32_t B, int32_t 
     return nlaunched("hgs_nn_mse");
 }
 
+hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32_t C, int32_t nz, int32_t ny,
+                         int32_t nx, int32_t ch, float w, float* scratch, uint16_t* grad, double* loss_dev,
+                         double* partials, void* stream) {
+    if (!out || !target || !scratch || !grad || !loss_dev || !partials) return nfail(HGS_ERR_ARG, "NULL argument");
+    if (B < 1 || C < 1 || C > NC || nz < 1 || ny < 1 || nx < 1 || ch < 0 || ch >= C)
+        return nfail(HGS_ERR_ARG, "need B, nz, ny, nx >= 1, 1 <= C <= 16, 0 <= ch < C");
+    if (!(w >= 0.f) || !std::isfinite(w)) return nfail(HGS_ERR_ARG, "w must be >= 0 and finite");
+    (void)hipGetLastError();
+    const int64_t nvox = (int64_t)nz * ny * nx;
+    const int nb = std::min(HGS_NN_MSE_PARTIALS, grid_of((int64_t)B * nvox));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const float inv = (float)(1.0 / ((double)B * C * nvox));
+    hipLaunchKernelGGL(k_lapres, dim3(grid_of((int64_t)B * nvox)), dim3(256), 0, st, out, target, B, C, ch, nz, ny, nx,
+                       scratch);
+    hipLaunchKernelGGL(k_lapmse, dim3(nb), dim3(256), 0, st, out, target, scratch, B, C, ch, nz, ny, nx, w, inv, grad,
+                       partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, partials, nb, loss_dev);
+    return nlaunched("hgs_nn_lapmse");
+}
+
 hgs_status hgs_nn_adam(float* p, float* m, float* v, const float* g, uint16_t* p16, int32_t n, float lr, float b1,
                        float b2, float eps, int32_t t, void* stream) {
     if (!p || !m || !v || !g) return nfail(HGS_ERR_ARG, "p, m, v and g must be non-NULL");

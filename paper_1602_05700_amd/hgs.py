@@ -31,7 +31,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 HGS_OK, HGS_ERR_ARG, HGS_ERR_CFL, HGS_ERR_WORKSPACE, HGS_ERR_DEVICE, HGS_ERR_NONFINITE, HGS_ERR_STATE = range(7)
 HGS_F64, HGS_F32 = 0, 1
-HGS_BC_MULTIPOLE, HGS_BC_USER = 0, 1
+HGS_BC_MULTIPOLE, HGS_BC_USER, HGS_BC_ROBIN, HGS_BC_OUTGOING, HGS_BC_PERIODIC = 0, 1, 2, 3, 4
+BC_NAMES = {"multipole": HGS_BC_MULTIPOLE, "user": HGS_BC_USER, "robin": HGS_BC_ROBIN,
+            "outgoing": HGS_BC_OUTGOING, "periodic": HGS_BC_PERIODIC}
 TMAX = 4
 LMAX = 4
 
@@ -63,6 +65,9 @@ _SIGS = {
     "hgs_get_boundary": (_i32, [_vp, _vp]),
     "hgs_moments": (_i32, [_vp, _dp]),
     "hgs_residual": (_i32, [_vp, _vp, _dp]),
+    "hgs_max_signal_speed": (_i32, [_vp, _vp, _vp, _vp, _vp, _dp]),
+    "hgs_hydro_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _dp, ctypes.POINTER(_i32), _dp]),
+    "hgs_energy": (_i32, [_vp, _vp, _dp]),
     "hgs_save_raw": (_i32, [_vp, _vp, _vp, _dp]),
     "hgs_load_raw": (_i32, [_vp, _vp, _vp, _dbl]),
     "hgs_set_tblock": (_i32, [_vp, _i32]),
@@ -83,6 +88,8 @@ _SIGS = {
     "hgs_nn_pack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_unpack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_mse": (_i32, [_vp, _vp, _i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]),
+    "hgs_nn_lapmse": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp,
+                             _vp]),
     "hgs_nn_adam": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                            ctypes.c_float, _i32, _vp]),
     "hgs_nn_restrict2": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
@@ -128,7 +135,7 @@ def make_config(shape, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, G: flo
     c.G = float(G)
     c.origin = (ctypes.c_double * 3)(*[float(v) for v in origin])
     c.lmax = int(lmax)
-    c.bc = {"multipole": HGS_BC_MULTIPOLE, "user": HGS_BC_USER}[bc]
+    c.bc = BC_NAMES[bc]
     c.storage = {"f64": HGS_F64, "f32": HGS_F32}[storage]
     c.tblock = int(tblock)
     c.eta = float(eta)
@@ -259,6 +266,39 @@ class Solver:
         _check(st, self._h)
         return res
 
+    def max_signal_speed(self, cs, v=None) -> float:
+        """max over cells of c_s + |v|; v = (vx, vy, vz) or None."""
+        self._need(cs)
+        vs = [None, None, None] if v is None else list(v)
+        for a in vs:
+            self._need(a)
+        out = ctypes.c_double(0.0)
+        _check(_lib.hgs_max_signal_speed(self._h, cs.data_ptr(), *(_ptr(a) for a in vs), ctypes.byref(out)), self._h)
+        return out.value
+
+    def hydro_step(self, rho, cs, v=None, k_g: float = 5.0, courant_hydro: float = 0.3,
+                   courant_grav: float = 0.3):
+        """One coupled hydrodynamical step (c_g = k_g max(c_s + |v|), nsub
+        substeps); returns (dt_hydro, nsub, c_g)."""
+        self._need(rho)
+        self._need(cs)
+        vs = [None, None, None] if v is None else list(v)
+        for a in vs:
+            self._need(a)
+        dth, cg = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        n = _i32(0)
+        _check(_lib.hgs_hydro_step(self._h, rho.data_ptr(), cs.data_ptr(), *(_ptr(a) for a in vs), float(k_g),
+                                   float(courant_hydro), float(courant_grav), ctypes.byref(dth), ctypes.byref(n),
+                                   ctypes.byref(cg)), self._h)
+        return dth.value, int(n.value), cg.value
+
+    def energy(self, rho) -> float:
+        """W = 1/2 sum rho phi dx^3 of the current potential."""
+        self._need(rho)
+        out = ctypes.c_double(0.0)
+        _check(_lib.hgs_energy(self._h, rho.data_ptr(), ctypes.byref(out)), self._h)
+        return out.value
+
     def save_raw(self):
         a, b = self._new(), self._new()
         dtp = ctypes.c_double(0.0)
@@ -301,7 +341,7 @@ class Solver:
 
 
 def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32", lmax: int = 4,
-             x0=(-1.0, -1.0, -1.0), dx=None, eta: float = 0.0, device="cuda", stream=None):
+             x0=(-1.0, -1.0, -1.0), dx=None, eta: float = 0.0, bc: str = "multipole", device="cuda", stream=None):
     """Fastest fused depth for hydro steps of nsub substeps on this grid (the
     library times every depth on a temporary workspace).  Returns
     (best_tblock, [ms per substep for depth 1..TMAX] or None when cached)."""
@@ -309,7 +349,7 @@ def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32",
 
     dev = torch.device(device)
     st = stream if stream is not None else torch.cuda.current_stream(dev)
-    cfg = make_config(shape, x0, dx, 1.0, (0.0, 0.0, 0.0), lmax, "multipole", storage, 0, eta, st.cuda_stream)
+    cfg = make_config(shape, x0, dx, 1.0, (0.0, 0.0, 0.0), lmax, bc, storage, 0, eta, st.cuda_stream)
     nb = workspace_bytes(cfg)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     best = _i32(0)
@@ -325,7 +365,7 @@ class Batch:
     substep group covering all grids, replayed from a captured hipGraph)."""
 
     def __init__(self, shapes, dxs=None, x0s=None, G: float = 1.0, lmax: int = 4, storage: str = "f32",
-                 tblock: int = 0, eta=0.0, device="cuda", stream=None):
+                 tblock: int = 0, eta=0.0, bc: str = "multipole", device="cuda", stream=None):
         import torch
 
         dev = torch.device(device)
@@ -342,7 +382,7 @@ class Batch:
             nz, ny, nx = (sh, sh, sh) if np.isscalar(sh) else sh
             dx = dxs[i] if dxs is not None else 2.0 / nx
             x0 = x0s[i] if x0s is not None else (-0.5 * nx * dx, -0.5 * ny * dx, -0.5 * nz * dx)
-            self.cfgs[i] = make_config((nz, ny, nx), x0, dx, G, (0.0, 0.0, 0.0), lmax, "multipole", storage,
+            self.cfgs[i] = make_config((nz, ny, nx), x0, dx, G, (0.0, 0.0, 0.0), lmax, bc, storage,
                                        tblock, etas[i], self.stream.cuda_stream)
         nb = _sz(0)
         _check(_lib.hgs_workspace_bytes_batch(self.cfgs, n, ctypes.byref(nb)))
@@ -468,6 +508,16 @@ def nn_mse(out, target, grad, loss_dev, partials):
     nvox = target[0, 0].numel()
     _nn_check(_lib.hgs_nn_mse(out.data_ptr(), target.data_ptr(), B, C, nvox, grad.data_ptr(), loss_dev.data_ptr(),
                               partials.data_ptr(), _stream_of(out)))
+
+
+def nn_lapmse(out, target, grad, loss_dev, partials, scratch, ch: int = 0, w: float = 1.0):
+    """target: planar (B, C, Z, Y, X) fp32; out: channels-last (B, Z, Y, X, 16)
+    fp32; scratch: fp32 with B*Z*Y*X elements."""
+    B, C, Z, Y, X = target.shape
+    assert scratch.numel() >= B * Z * Y * X
+    _nn_check(_lib.hgs_nn_lapmse(out.data_ptr(), target.data_ptr(), B, C, Z, Y, X, int(ch), float(w),
+                                 scratch.data_ptr(), grad.data_ptr(), loss_dev.data_ptr(), partials.data_ptr(),
+                                 _stream_of(out)))
 
 
 def nn_adam(p, m, v, g, p16, lr, t, b1=0.9, b2=0.999, eps=1e-8):

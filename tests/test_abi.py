@@ -48,7 +48,7 @@ def test_config_cube_defaults():
 
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("ny", -3), ("nz", 9000), ("dx", 0.0), ("dx", float("nan")), ("lmax", 5), ("lmax", -1),
-    ("bc", 2), ("storage", 7), ("tblock", 5), ("tblock", -1), ("eta", -0.5), ("eta", float("inf")),
+    ("bc", 5), ("bc", -1), ("storage", 7), ("tblock", 5), ("tblock", -1), ("eta", -0.5), ("eta", float("inf")),
     ("G", float("nan")),
 ])
 def test_bad_config_rejected(field, value):
@@ -138,3 +138,19 @@ def test_multipole_centre_must_be_inside():
     assert L.hgs_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == hgs.HGS_OK
     c = hgs.make_config(8, origin=(1.0, 0.0, 0.0))  # on the face: a ghost could sit at r = 0
     assert L.hgs_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == hgs.HGS_ERR_ARG
+
+
+def test_local_boundaries_host_checks():
+    L = hgs.library()
+    n = ctypes.c_size_t(0)
+    for bc in ("robin", "outgoing"):  # r-weighted rules need the centre inside
+        c = hgs.make_config((3, 2, 5), bc=bc)
+        assert L.hgs_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == hgs.HGS_ERR_ARG
+        c = hgs.make_config(8, bc=bc)
+        assert L.hgs_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == hgs.HGS_OK
+    c = hgs.make_config((3, 2, 5), bc="periodic")  # no centre involved
+    assert L.hgs_workspace_bytes(ctypes.byref(c), ctypes.byref(n)) == hgs.HGS_OK
+    # batches need a boundary frozen over the step
+    cfgs = (hgs.Config * 2)(hgs.make_config(16), hgs.make_config(16, bc="robin"))
+    assert L.hgs_workspace_bytes_batch(cfgs, 2, ctypes.byref(n)) == hgs.HGS_ERR_ARG
+    assert b"frozen" in L.hgs_last_error(None)

@@ -1,0 +1,140 @@
+"""The hydro-coupled driver on the GPU: c_g = k_g max(c_s + |v|) (Eq. 3),
+k_g-fold sub-cycling (Sec. 2), the gravitational energy W, and the paper's
+error estimate |phi_E / phi| ~ (c_s^2 + v^2) / c_g^2 (Eq. 12) measured against
+the Poisson solution of the same frozen density (the P model of Sec. 3)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import core, poisson
+from oracle.core import Oracle, interior, padded
+from test_gpu_parity import F64_TOL, dens, grid_of, host, rel, solver, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_max_signal_speed(gpu_lib, storage):
+    shape = (19, 23, 40)
+    rng = np.random.default_rng(30)
+    dt = np.float64 if storage == "f64" else np.float32
+    cs = rng.uniform(0.1, 1.0, shape).astype(dt)
+    v = [rng.normal(0, 0.5, shape).astype(dt) for _ in range(3)]
+    s = solver(gpu_lib, shape, storage=storage)
+    want = np.max(cs.astype(np.float64) + np.sqrt(sum(a.astype(np.float64) ** 2 for a in v)))
+    got = s.max_signal_speed(to_dev(cs), [to_dev(a) for a in v])
+    assert got == pytest.approx(want, rel=1e-15)
+    assert s.max_signal_speed(to_dev(cs)) == pytest.approx(float(np.max(cs.astype(np.float64))), rel=0)
+    bad = v[0].copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(gpu_lib.HGSError):
+        s.max_signal_speed(to_dev(cs), [to_dev(bad), to_dev(v[1]), to_dev(v[2])])
+
+
+def test_hydro_step_is_the_sub_cycled_step(gpu_lib):
+    """hgs_hydro_step = hgs_step(rho, k_g vmax, dt_h / nsub, nsub) with
+    dt_h = C_h dx / vmax and nsub = ceil(k_g C_h / C_g), bitwise."""
+    shape = (24, 20, 28)
+    g = grid_of(shape)
+    rho = to_dev(dens(shape, 31, "f64"))
+    rng = np.random.default_rng(31)
+    cs = to_dev(rng.uniform(0.05, 0.2, shape))
+    v = [to_dev(rng.normal(0, 0.1, shape)) for _ in range(3)]
+    vmax = max(float(np.max(host(cs) + np.sqrt(sum(host(a) ** 2 for a in v)))), 1e-300)
+    for k_g, ch, cg in ((5.0, 0.3, 0.3), (2.5, 0.4, 0.5), (7.0, 0.3, 0.2)):
+        a = solver(gpu_lib, shape, storage="f64")
+        b = solver(gpu_lib, shape, storage="f64")
+        for _ in range(2):
+            dth, nsub, c_g = a.hydro_step(rho, cs, v, k_g=k_g, courant_hydro=ch, courant_grav=cg)
+            assert nsub == math.ceil(k_g * ch / cg - 1e-9)
+            assert dth == pytest.approx(ch * g.dx / vmax, rel=1e-14)
+            assert c_g == pytest.approx(k_g * vmax, rel=1e-14)
+            b.step(rho, c_g, dth / nsub, nsub)
+        assert np.array_equal(host(a.potential()[0]), host(b.potential()[0]))
+    with pytest.raises(gpu_lib.HGSError):
+        a.hydro_step(rho, cs, v, k_g=0.5)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_energy(gpu_lib, storage):
+    """W = 1/2 sum rho phi dx^3 of the current potential, against the same
+    sum of the GPU's and the oracle's potential."""
+    shape = (30, 26, 33)
+    g = grid_of(shape)
+    rho = dens(shape, 32, storage)
+    r64 = rho.astype(np.float64)
+    s = solver(gpu_lib, shape, storage=storage, eta=2.0)
+    o = Oracle(g, eta=2.0)
+    s.step(to_dev(rho), 1.0, 0.4 * g.dx, 40)
+    o.step(r64, 1.0, 0.4 * g.dx, 40)
+    w = s.energy(to_dev(rho))
+    dv = g.dx ** 3
+    assert w == pytest.approx(0.5 * np.sum(r64 * host(s.potential()[0])) * dv, rel=1e-12)
+    tol = F64_TOL if storage == "f64" else 1e-4
+    assert w == pytest.approx(0.5 * np.sum(r64 * o.potential()[0]) * dv, rel=tol)
+
+
+def _poisson(g, rho):
+    q = core.moments(g, rho, 4)
+    P = padded(g)
+    core.boundary(g, q, 4, 1.0, P)
+    return poisson.solve_dst(g, rho, 1.0, P)
+
+
+def _h_vs_p_error(hgs, k_g, n=32, omega=0.5, ch=0.075, steps=240):
+    """Mean relative difference <|phi_H - phi_P|> / <|phi_P|> over the last
+    third of a run in which a blob mixture rotates rigidly about z, coupled
+    through hgs_hydro_step (multipole boundary, eta = 0, c_s = 0)."""
+    import torch
+
+    shape = (n, n, n)
+    g = grid_of(shape)
+    base = workloads.blob_params(3, 6)
+    x, y, z = workloads.centred_axes(shape, g.dx)
+    rho_at = lambda t: workloads.blob_density_axes(x, y, z, base.rotated(omega * t), dtype=np.float64)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    vx, vy = to_dev(-omega * Y), to_dev(omega * X)
+    vz = torch.zeros_like(vx)
+    cs = torch.zeros_like(vx)
+    vmax = omega * float(np.sqrt(X ** 2 + Y ** 2).max())
+    # start: the Poisson solution and the time derivative of rigid rotation,
+    # d phi / dt = -omega (x d/dy - y d/dx) phi
+    phi0 = _poisson(g, rho_at(0.0))
+    Pf = padded(g)
+    interior(Pf)[...] = phi0
+    q = core.moments(g, rho_at(0.0), 4)
+    core.boundary(g, q, 4, 1.0, Pf)
+    dpx = (Pf[1:-1, 1:-1, 2:] - Pf[1:-1, 1:-1, :-2]) / (2 * g.dx)
+    dpy = (Pf[1:-1, 2:, 1:-1] - Pf[1:-1, :-2, 1:-1]) / (2 * g.dx)
+    pd0 = -omega * (X * dpy - Y * dpx)
+    s = solver(hgs, shape, storage="f64")
+    dth = ch * g.dx / vmax
+    nsub = math.ceil(k_g * ch / 0.3 - 1e-9)
+    s.set_state(to_dev(phi0), to_dev(pd0), dth / nsub)
+    errs, t = [], 0.0
+    for h in range(steps):
+        rho = rho_at(t + 0.5 * dth)  # frozen over the hydrodynamical step
+        dt_h, _, _ = s.hydro_step(to_dev(rho), cs, (vx, vy, vz), k_g=k_g, courant_hydro=ch, courant_grav=0.3)
+        t += dt_h
+        if h >= steps - steps // 3 and h % (steps // 15) == 0:
+            ref = _poisson(g, rho)
+            errs.append(np.mean(np.abs(host(s.potential()[0]) - ref)) / np.mean(np.abs(ref)))
+    return float(np.mean(errs)), vmax
+
+
+def test_error_estimate_eq12(gpu_lib):
+    """The difference from the Poisson solution falls with k_g; between k_g = 2
+    and 4, where the O((v / c_g)^2) term of Eq. 12 dominates the O(dt_hydro)
+    floor of the frozen density, by more than the factor 2 a first-order term
+    would give (second order: 4).  All stay below (v_max / c_g)^2 = 1 / k_g^2."""
+    errs = {}
+    for k_g in (2.0, 4.0, 8.0, 16.0):
+        errs[k_g], vmax = _h_vs_p_error(gpu_lib, k_g)
+    ks = sorted(errs)
+    for a, b in zip(ks, ks[1:]):
+        assert errs[b] <= errs[a] * 1.05, errs
+    assert errs[2.0] / errs[4.0] > 2.5, errs
+    for k in ks:
+        assert errs[k] < 1.0 / k ** 2, errs

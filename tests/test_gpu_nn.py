@@ -147,3 +147,29 @@ def test_adam_mse_pack(gpu_lib):
     back = torch.empty((B, C, 4, 5, 16), dtype=torch.float32, device="cuda")
     hgs.nn_unpack(out, C, back)
     assert np.array_equal(_h(back), np.moveaxis(_h(out)[..., :C], -1, 1))
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 5, 4, 7), (1, 3, 9, 6, 16)])
+def test_lapmse_matches_oracle(gpu_lib, shape):
+    """Laplacian-weighted loss and its gradient against the FP64 oracle
+    (differences formed exactly from FP32 inputs; gradient rounded to bf16)."""
+    import torch
+
+    hgs = gpu_lib
+    B, C, Z, Y, X = shape
+    rng = np.random.default_rng(12)
+    out = rng.standard_normal((B, Z, Y, X, 16)).astype(np.float32)
+    tgt = rng.standard_normal((B, C, Z, Y, X)).astype(np.float32)
+    w, ch = 0.6, C - 1
+    grad = torch.empty((B, Z, Y, X, 16), dtype=torch.bfloat16, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    parts = torch.empty(hgs.NN_MSE_PARTIALS, dtype=torch.float64, device="cuda")
+    scratch = torch.empty(B * Z * Y * X, dtype=torch.float32, device="cuda")
+    hgs.nn_lapmse(_t(out, torch.float32), _t(tgt, torch.float32), grad, loss, parts, scratch, ch=ch, w=w)
+    o = np.moveaxis(out[..., :C].astype(np.float64), -1, 1)
+    ref_loss, ref_g = nn.lap_mse(o, tgt.astype(np.float64), ch, w)
+    n = B * C * Z * Y * X
+    assert float(loss.item()) == pytest.approx(ref_loss * n, rel=1e-6)
+    gh = np.moveaxis(_h(grad)[..., :C], -1, 1)
+    assert np.all(np.abs(gh - ref_g) <= 2.0 ** -8 * np.abs(ref_g) + 1e-6 * np.max(np.abs(ref_g)))
+    assert np.all(_h(grad)[..., C:] == 0)

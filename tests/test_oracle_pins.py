@@ -451,3 +451,25 @@ def test_f32_storage_emulation_close_to_f64():
     assert np.all(pb == pb.astype(np.float32).astype(np.float64))
     err = np.max(np.abs(pa - pb)) / np.max(np.abs(pa))
     assert 0 < err < 1e-5
+
+
+def test_energy_of_uniform_sphere_converges_to_closed_form():
+    """W = 1/2 sum rho phi dV of the discrete Poisson solution of a uniform
+    sphere tends to -3 G M^2 / (5 R) at second order (M, R of the voxelised
+    sphere)."""
+    from oracle import core, poisson
+
+    errs = []
+    for n in (24, 48):
+        g = Grid.cube(n)
+        x, y, z = (c[1:-1] for c in g.centres())
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        rho = (X ** 2 + Y ** 2 + Z ** 2 < 0.25).astype(float)
+        dv = g.dx ** 3
+        M = rho.sum() * dv
+        R = (3.0 * M / (4.0 * np.pi)) ** (1.0 / 3.0)
+        P = core.padded(g)
+        core.boundary(g, core.moments(g, rho, 0), 0, 1.0, P)
+        W = core.energy(g, rho, poisson.solve_dst(g, rho, 1.0, P))
+        errs.append(abs(W / (-0.6 * M * M / R) - 1.0))
+    assert errs[1] < 2e-3 and errs[0] / errs[1] > 3.0, errs
