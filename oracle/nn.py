@@ -19,6 +19,11 @@ plain definition written out in NumPy, in FP64:
   Laplacian (zero outside, index units) of one channel's error, and its
   gradient -- the residual of the predicted potential is what sets the
   solver's steps from a warm start, and it weighs fine-scale error heavily;
+* the network's input features (density and coarse potential scaled by the
+  sample's peak density, and the coarse potential's 7-point residual of the
+  discrete Poisson equation, Eq. 1, with the second difference along an axis
+  taken as 0 at the first and last cell) and the composition of the output
+  into (phi, dphi/dt);
 * bfloat16 round-to-nearest-even (for feeding the oracle the same rounded
   values as the device).
 """
@@ -144,6 +149,43 @@ def lap_mse(out: np.ndarray, target: np.ndarray, ch: int, w: float):
     g = 2.0 * e / n
     g[:, ch] += 2.0 * w * lap7(r) / n  # lap7 is symmetric (zero padding)
     return loss, g
+
+
+def lap7_ext(f: np.ndarray) -> np.ndarray:
+    """7-point Laplacian in index units over the last three axes; along each
+    axis the second difference f[i-1] - 2 f[i] + f[i+1] is taken as 0 at the
+    first and last cell (a linear extension across the faces)."""
+    f = np.asarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    for ax in (-3, -2, -1):
+        n = f.shape[ax]
+        if n < 3:
+            continue
+        fm = np.take(f, np.arange(0, n - 2), axis=ax)
+        fc = np.take(f, np.arange(1, n - 1), axis=ax)
+        fp = np.take(f, np.arange(2, n), axis=ax)
+        d = fm - 2.0 * fc + fp
+        idx = [slice(None)] * f.ndim
+        idx[ax] = slice(1, n - 1)
+        out[tuple(idx)] += d
+    return out
+
+
+def features(rho: np.ndarray, phi: np.ndarray, scale: np.ndarray, c: float) -> np.ndarray:
+    """Inputs (B, 3, Z, Y, X) of the warm-start network from rho and a coarse
+    potential phi (B, Z, Y, X) on a grid of spacing h, c = 4 pi G h^2, and the
+    per-sample scale s (B,): rho / s, phi / s, (lap7_ext(phi) - c rho) / (c s)."""
+    s = np.asarray(scale, dtype=np.float64).reshape(-1, 1, 1, 1)
+    rho = np.asarray(rho, dtype=np.float64)
+    phi = np.asarray(phi, dtype=np.float64)
+    return np.stack([rho / s, phi / s, (lap7_ext(phi) - c * rho) / (c * s)], axis=1)
+
+
+def compose(phi_c: np.ndarray, out: np.ndarray, scale: np.ndarray, out_scale: float):
+    """(phi, dphi/dt) from the coarse potential (B, Z, Y, X) and the network
+    output (B, 2, Z, Y, X) in units of s / out_scale."""
+    f = np.asarray(scale, dtype=np.float64).reshape(-1, 1, 1, 1) / out_scale
+    return phi_c + out[:, 0] * f, out[:, 1] * f
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:

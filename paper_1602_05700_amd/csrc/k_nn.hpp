@@ -318,6 +318,60 @@ __global__ __launch_bounds__(256) void k_lapmse(const float* __restrict__ out, c
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Per-sample peak |x| over nvox values: one workgroup per sample.
+__global__ __launch_bounds__(256) void k_maxabs(const float* __restrict__ x, int64_t nvox, float* __restrict__ out) {
+    __shared__ float red[4];
+    const float* p = x + (int64_t)blockIdx.x * nvox;
+    float m = 0.f;
+    for (int64_t t = threadIdx.x; t < nvox; t += blockDim.x) m = fmaxf(m, fabsf(p[t]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// second difference along one axis, 0 at the first and last cell
+__device__ __forceinline__ double d2_ext(const float* __restrict__ f, int i, int n, int64_t stride) {
+    if (i <= 0 || i >= n - 1) return 0.0;
+    return ((double)f[-stride] + (double)f[stride]) - 2.0 * (double)f[0];
+}
+
+// Network inputs, planar [B][3][Z][Y][X] FP32:
+//   rho / s, phi / s, (L_ext phi - c rho) / (c s),  c = 4 pi G h^2, s = scale[b],
+// L_ext the 7-point Laplacian in index units with the second difference along
+// an axis taken as 0 at the first and last cell.
+__global__ __launch_bounds__(256) void k_features(const float* __restrict__ rho, const float* __restrict__ phi,
+                                                  const float* __restrict__ scale, int B, int nz, int ny, int nx,
+                                                  double c, float* __restrict__ out) {
+    const int64_t nvox = (int64_t)nz * ny * nx, total = (int64_t)B * nvox;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t / nvox, v = t % nvox;
+        const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((int64_t)nx * ny));
+        const float* pf = phi + t;
+        const double lap = (d2_ext(pf, i, nx, 1) + d2_ext(pf, j, ny, nx)) + d2_ext(pf, k, nz, (int64_t)nx * ny);
+        const double s = (double)scale[b];
+        const double r = (double)rho[t];
+        float* o = out + b * 3 * nvox + v;
+        o[0] = (float)(r / s);
+        o[nvox] = (float)((double)pf[0] / s);
+        o[2 * nvox] = (float)((lap - c * r) / (c * s));
+    }
+}
+
+// (phi, dphi/dt) = (phi_c + y0 s f, y1 s f) from the last layer's FP32
+// channels-last output y, f = 1 / out_scale.
+__global__ __launch_bounds__(256) void k_compose(const float* __restrict__ phi_c, const float* __restrict__ y,
+                                                 const float* __restrict__ scale, int B, int64_t nvox, double inv_out,
+                                                 float* __restrict__ phi, float* __restrict__ phidot) {
+    const int64_t total = (int64_t)B * nvox;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const double f = (double)scale[t / nvox] * inv_out;
+        phi[t] = (float)((double)phi_c[t] + (double)y[t * NC] * f);
+        if (phidot) phidot[t] = (float)((double)y[t * NC + 1] * f);
+    }
+}
+
 __global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         double s = 0.0;

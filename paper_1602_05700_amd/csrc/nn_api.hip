@@ -139,6 +139,38 @@ hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32
     return nlaunched("hgs_nn_lapmse");
 }
 
+hgs_status hgs_nn_maxabs(const float* x, int32_t B, int64_t nvox, float* out, void* stream) {
+    if (!x || !out) return nfail(HGS_ERR_ARG, "x and out must be non-NULL");
+    if (B < 1 || nvox < 1) return nfail(HGS_ERR_ARG, "need B >= 1 and nvox >= 1");
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_maxabs, dim3(B), dim3(256), 0, static_cast<hipStream_t>(stream), x, nvox, out);
+    return nlaunched("hgs_nn_maxabs");
+}
+
+hgs_status hgs_nn_features(const float* rho, const float* phi, const float* scale, int32_t B, int32_t nz, int32_t ny,
+                           int32_t nx, double c, float* out, void* stream) {
+    if (!rho || !phi || !scale || !out) return nfail(HGS_ERR_ARG, "NULL argument");
+    if (B < 1 || nz < 1 || ny < 1 || nx < 1) return nfail(HGS_ERR_ARG, "need B, nz, ny, nx >= 1");
+    if (!(c > 0.0) || !std::isfinite(c)) return nfail(HGS_ERR_ARG, "c must be positive and finite");
+    (void)hipGetLastError();
+    const int64_t n = (int64_t)B * nz * ny * nx;
+    hipLaunchKernelGGL(k_features, dim3(grid_of(n)), dim3(256), 0, static_cast<hipStream_t>(stream), rho, phi, scale, B,
+                       nz, ny, nx, c, out);
+    return nlaunched("hgs_nn_features");
+}
+
+hgs_status hgs_nn_compose(const float* phi_c, const float* y, const float* scale, int32_t B, int64_t nvox,
+                          double inv_out_scale, float* phi, float* phidot, void* stream) {
+    if (!phi_c || !y || !scale || !phi) return nfail(HGS_ERR_ARG, "phi_c, y, scale and phi must be non-NULL");
+    if (B < 1 || nvox < 1) return nfail(HGS_ERR_ARG, "need B >= 1 and nvox >= 1");
+    if (!std::isfinite(inv_out_scale)) return nfail(HGS_ERR_ARG, "inv_out_scale must be finite");
+    (void)hipGetLastError();
+    const int64_t n = (int64_t)B * nvox;
+    hipLaunchKernelGGL(k_compose, dim3(grid_of(n)), dim3(256), 0, static_cast<hipStream_t>(stream), phi_c, y, scale, B,
+                       nvox, inv_out_scale, phi, phidot);
+    return nlaunched("hgs_nn_compose");
+}
+
 hgs_status hgs_nn_adam(float* p, float* m, float* v, const float* g, uint16_t* p16, int32_t n, float lr, float b1,
                        float b2, float eps, int32_t t, void* stream) {
     if (!p || !m || !v || !g) return nfail(HGS_ERR_ARG, "p, m, v and g must be non-NULL");

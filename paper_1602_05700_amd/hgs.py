@@ -88,6 +88,9 @@ _SIGS = {
     "hgs_nn_pack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_unpack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_mse": (_i32, [_vp, _vp, _i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]),
+    "hgs_nn_maxabs": (_i32, [_vp, _i32, ctypes.c_int64, _vp, _vp]),
+    "hgs_nn_features": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _dbl, _vp, _vp]),
+    "hgs_nn_compose": (_i32, [_vp, _vp, _vp, _i32, ctypes.c_int64, _dbl, _vp, _vp, _vp]),
     "hgs_nn_lapmse": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp,
                              _vp]),
     "hgs_nn_adam": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -518,6 +521,30 @@ def nn_lapmse(out, target, grad, loss_dev, partials, scratch, ch: int = 0, w: fl
     _nn_check(_lib.hgs_nn_lapmse(out.data_ptr(), target.data_ptr(), B, C, Z, Y, X, int(ch), float(w),
                                  scratch.data_ptr(), grad.data_ptr(), loss_dev.data_ptr(), partials.data_ptr(),
                                  _stream_of(out)))
+
+
+def nn_maxabs(x, out):
+    """x: (B, ...) fp32; out: (B,) fp32 receives the per-sample max |x|."""
+    B = x.shape[0]
+    assert out.numel() == B and x.is_contiguous()
+    _nn_check(_lib.hgs_nn_maxabs(x.data_ptr(), B, x[0].numel(), out.data_ptr(), _stream_of(x)))
+
+
+def nn_features(rho, phi, scale, c: float, out):
+    """rho, phi: (B, Z, Y, X) fp32; scale: (B,) fp32; out: (B, 3, Z, Y, X) fp32."""
+    B, Z, Y, X = rho.shape
+    assert tuple(phi.shape) == tuple(rho.shape) and tuple(out.shape) == (B, 3, Z, Y, X) and scale.numel() == B
+    _nn_check(_lib.hgs_nn_features(rho.data_ptr(), phi.data_ptr(), scale.data_ptr(), B, Z, Y, X, float(c),
+                                   out.data_ptr(), _stream_of(rho)))
+
+
+def nn_compose(phi_c, y, scale, out_scale: float, phi, phidot=None):
+    """phi_c, phi, phidot: (B, Z, Y, X) fp32; y: (B, Z, Y, X, 16) fp32."""
+    B = phi_c.shape[0]
+    nvox = phi_c[0].numel()
+    assert y.numel() == B * nvox * NN_CHANNELS and phi.shape == phi_c.shape and scale.numel() == B
+    _nn_check(_lib.hgs_nn_compose(phi_c.data_ptr(), y.data_ptr(), scale.data_ptr(), B, nvox,
+                                  float(1.0 / out_scale), phi.data_ptr(), _ptr(phidot), _stream_of(phi_c)))
 
 
 def nn_adam(p, m, v, g, p16, lr, t, b1=0.9, b2=0.999, eps=1e-8):

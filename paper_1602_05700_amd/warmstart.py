@@ -9,9 +9,9 @@ The paper starts its runs from a Poisson solution or an interpolated exact one
      critical damping) gives a coarse potential, prolonged to n/2 -- the global
      cue a local network cannot build by itself;
   3. a 4-layer 3x3x3 convolution network (16 channels, tanh, bf16 weights and
-     activations, FP32 accumulation) maps (rho, coarse phi) at n/2 to a
-     correction of phi and to dphi/dt, in units scaled by max(rho) because phi
-     is linear in rho;
+     activations, FP32 accumulation) maps (rho, coarse phi, the coarse phi's
+     residual of the discrete Eq. 1) at n/2 to a correction of phi and to
+     dphi/dt, in units scaled by max(rho) because phi is linear in rho;
   4. the n/2 prediction is prolonged to n and handed to hgs_set_state.
 
 The zero start stays the fallback: if the warm start's residual is not below
@@ -30,7 +30,7 @@ from . import hgs
 
 NC = hgs.NN_CHANNELS
 N_LAYERS = 4
-IN_CH = 2   # rho, coarse phi
+IN_CH = 3   # rho, coarse phi, its residual of the discrete Poisson equation
 OUT_CH = 2  # phi correction, dphi/dt
 
 
@@ -185,15 +185,19 @@ class Features:
         return self.coarse_steps * (self.nq / self.n) ** 3
 
     def inputs(self, rho):
-        """Planar network inputs (B, 2, n/2^3) fp32, the coarse phi at n/2 and the
-        per-sample scale max(rho)."""
+        """Planar network inputs (B, 3, n/2^3) fp32, the coarse phi at n/2 and the
+        per-sample scale max|rho| (B,) fp32.  rho: (B, n, n, n) fp32, positive
+        somewhere in every sample."""
         import torch
 
+        B = rho.shape[0]
         r2, r4 = self.restrict(rho)
         phi2 = self.coarse_phi(r4)
-        scale = rho.reshape(rho.shape[0], -1).amax(dim=1).clamp_min(1e-30)
-        s = scale.view(-1, 1, 1, 1)
-        planar = torch.stack([r2 / s, phi2 / s], dim=1).contiguous()
+        scale = torch.empty(B, dtype=torch.float32, device=rho.device)
+        hgs.nn_maxabs(rho, scale)
+        h = 2.0 * (2.0 / self.n)
+        planar = torch.empty((B, IN_CH) + tuple(r2.shape[1:]), dtype=torch.float32, device=rho.device)
+        hgs.nn_features(r2, phi2, scale, 4.0 * math.pi * h * h, planar)
         return planar, phi2, scale
 
 
@@ -213,11 +217,10 @@ def predict_fine(net: Net, planar, phi2, scale, n: int):
     B = planar.shape[0]
     x = pack(planar)
     out = net.forward(x)[-1]
-    pl = torch.empty((B, OUT_CH) + tuple(planar.shape[2:]), dtype=torch.float32, device=planar.device)
-    hgs.nn_unpack(out, OUT_CH, pl)
-    s = scale.view(-1, 1, 1, 1) / net.out_scale
-    phi2 = (phi2 + pl[:, 0] * s).contiguous()
-    pd2 = (pl[:, 1] * s).contiguous()
+    phi2f = torch.empty_like(phi2)
+    pd2 = torch.empty_like(phi2)
+    hgs.nn_compose(phi2, out, scale, net.out_scale, phi2f, pd2)
+    phi2 = phi2f
     phi = torch.empty((B, n, n, n), dtype=torch.float32, device=planar.device)
     pd = torch.empty_like(phi)
     hgs.nn_prolong2(phi2, phi)

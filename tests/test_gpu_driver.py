@@ -125,16 +125,19 @@ def _h_vs_p_error(hgs, k_g, n=32, omega=0.5, ch=0.075, steps=240):
 
 
 def test_error_estimate_eq12(gpu_lib):
-    """The difference from the Poisson solution falls with k_g; between k_g = 2
-    and 4, where the O((v / c_g)^2) term of Eq. 12 dominates the O(dt_hydro)
-    floor of the frozen density, by more than the factor 2 a first-order term
-    would give (second order: 4).  All stay below (v_max / c_g)^2 = 1 / k_g^2."""
+    """The difference from the Poisson solution falls with k_g toward a floor
+    set by the frozen density (first order in dt_hydro, independent of k_g).
+    Above that floor (taken as the k_g = 16 value) it falls from k_g = 2 to 4
+    by more than a first-order term in v / c_g allows, (1/2 - 1/16) /
+    (1/4 - 1/16) = 2.33; second order, as Eq. 12 estimates, gives 4.2.  All stay
+    below (v_max / c_g)^2 = 1 / k_g^2."""
     errs = {}
     for k_g in (2.0, 4.0, 8.0, 16.0):
         errs[k_g], vmax = _h_vs_p_error(gpu_lib, k_g)
     ks = sorted(errs)
     for a, b in zip(ks, ks[1:]):
         assert errs[b] <= errs[a] * 1.05, errs
-    assert errs[2.0] / errs[4.0] > 2.5, errs
+    floor = errs[16.0]
+    assert (errs[2.0] - floor) / (errs[4.0] - floor) > 2.8, errs
     for k in ks:
         assert errs[k] < 1.0 / k ** 2, errs

@@ -173,3 +173,30 @@ def test_lapmse_matches_oracle(gpu_lib, shape):
     gh = np.moveaxis(_h(grad)[..., :C], -1, 1)
     assert np.all(np.abs(gh - ref_g) <= 2.0 ** -8 * np.abs(ref_g) + 1e-6 * np.max(np.abs(ref_g)))
     assert np.all(_h(grad)[..., C:] == 0)
+
+
+def test_features_maxabs_compose_match_oracle(gpu_lib):
+    import torch
+
+    hgs = gpu_lib
+    rng = np.random.default_rng(13)
+    B, Z, Y, X = 2, 5, 7, 9
+    rho = rng.uniform(0.0, 3.0, (B, Z, Y, X)).astype(np.float32)
+    rho[1] *= -1.0  # max |x|, not max x
+    phi = rng.standard_normal((B, Z, Y, X)).astype(np.float32)
+    s = torch.empty(B, dtype=torch.float32, device="cuda")
+    hgs.nn_maxabs(_t(rho, torch.float32), s)
+    assert np.array_equal(_h(s), np.abs(rho).reshape(B, -1).max(axis=1).astype(np.float64))
+    c = 4.0 * np.pi * 0.03 ** 2
+    out = torch.empty((B, 3, Z, Y, X), dtype=torch.float32, device="cuda")
+    hgs.nn_features(_t(rho, torch.float32), _t(phi, torch.float32), s, c, out)
+    ref = nn.features(rho.astype(np.float64), phi.astype(np.float64), _h(s), c)
+    # FP64 arithmetic on FP32 inputs, rounded once to FP32
+    assert np.all(np.abs(_h(out) - ref) <= 2.0 ** -23 * np.abs(ref) + 1e-30)
+    y = rng.standard_normal((B, Z, Y, X, 16)).astype(np.float32)
+    p = torch.empty((B, Z, Y, X), dtype=torch.float32, device="cuda")
+    d = torch.empty_like(p)
+    hgs.nn_compose(_t(phi, torch.float32), _t(y, torch.float32), s, 3.0, p, d)
+    rp, rd = nn.compose(phi.astype(np.float64), np.moveaxis(y[..., :2], -1, 1).astype(np.float64), _h(s), 3.0)
+    assert np.all(np.abs(_h(p) - rp) <= 2.0 ** -23 * np.abs(rp) + 1e-30)
+    assert np.all(np.abs(_h(d) - rd) <= 2.0 ** -23 * np.abs(rd) + 1e-30)

@@ -62,7 +62,7 @@ def test_small_end_to_end(gpu_lib):
     rho = torch.stack([workloads.blob_density_torch(n, workloads.warmstart_blobs(s), "cuda", torch.float32)
                        for s in range(5)])
     planar, phi2, scale = feats.inputs(rho)
-    assert planar.shape == (5, 2, 16, 16, 16) and torch.isfinite(planar).all()
+    assert planar.shape == (5, 3, 16, 16, 16) and torch.isfinite(planar).all()
     phis, res = ws.converged_phi(list(rho), n, "cuda", steps=600)
     assert max(res) < 1e-8
     ex2 = torch.empty_like(phi2)

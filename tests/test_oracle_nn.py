@@ -151,3 +151,34 @@ def test_lap7_and_lap_mse_gradient():
         assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-9)
     # w = 0 is the plain mean-squared error
     assert nn.lap_mse(out, tgt, 0, 0.0)[0] == pytest.approx(np.mean((out - tgt) ** 2), rel=1e-14)
+
+
+def test_lap7_ext_and_features_pins():
+    z, y, x = np.meshgrid(np.arange(6.0), np.arange(5.0), np.arange(7.0), indexing="ij")
+    # linear fields: the linear extension across the faces makes it exact (0)
+    lin = (0.3 * x - 1.2 * y + 2.0 * z + 0.7)[None]
+    assert np.allclose(nn.lap7_ext(lin), 0.0, atol=1e-12)
+    # x^2: 2 in the interior along x, 0 on the first and last cell of x
+    q = (x ** 2)[None]
+    L = nn.lap7_ext(q)[0]
+    assert np.allclose(L[:, :, 1:-1], 2.0) and np.allclose(L[:, :, [0, -1]], 0.0)
+    # the residual feature of the discrete Poisson solution vanishes at cells
+    # whose 7-point stencil lies inside the grid (Eq. 1 in discrete form)
+    from oracle import core, poisson
+    g = core.Grid.cube(16)
+    xc, yc, zc = (c[1:-1] for c in g.centres())
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    rho = np.exp(-((X - 0.1) ** 2 + Y ** 2 + (Z + 0.2) ** 2) / 0.05)
+    P = core.padded(g)
+    core.boundary(g, core.moments(g, rho, 4), 4, 1.0, P)
+    phi = poisson.solve_dst(g, rho, 1.0, P)
+    c = 4.0 * np.pi * g.dx ** 2
+    f = nn.features(rho[None], phi[None], np.array([rho.max()]), c)
+    assert f.shape == (1, 3, 16, 16, 16)
+    assert np.allclose(f[0, 0], rho / rho.max()) and np.allclose(f[0, 1], phi / rho.max())
+    assert np.max(np.abs(f[0, 2, 1:-1, 1:-1, 1:-1])) < 1e-10
+    assert np.max(np.abs(f[0, 2])) > 1e-3  # the face cells see the truncated stencil
+    # compose inverts the scaling
+    out = np.random.default_rng(0).standard_normal((1, 2, 16, 16, 16))
+    p, d = nn.compose(phi[None], out, np.array([2.0]), 4.0)
+    assert np.allclose(p, phi[None] + 0.5 * out[:, 0]) and np.allclose(d, 0.5 * out[:, 1])
