@@ -119,6 +119,47 @@ def run_batched(dev, nsub=500, seed=2, count=64):
             "graph": b.used_graph, "tblock": b.grids[0].tblock}
 
 
+def run_warmstart(dev, count=8, n=128, tol=1e-4):
+    """Substeps of the critically damped FP32 solver to R_b < tol on 128^3
+    blob mixtures (held-out seeds 20000..), from the zero start and from the
+    learned start with the committed weights (zero start as fallback); the
+    coarse solve that feeds the network is counted in fine-substep
+    equivalents."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import warmstart as ws
+
+    if not os.path.exists(ws.WEIGHTS):
+        return {"skipped": "no trained weights in the package"}
+    net = ws.Net.load(ws.WEIGHTS, dev)
+    feats = ws.Features(n, dev, coarse_steps=net.coarse_steps)
+    seeds = list(range(20000, 20000 + count))
+    rho = torch.stack([workloads.blob_density_torch(n, workloads.warmstart_blobs(s), dev, torch.float32)
+                       for s in seeds])
+    t0 = time.perf_counter()
+    planar, phi2, scale = feats.inputs(rho)
+    phi, pd = ws.predict_fine(net, planar, phi2, scale, n)
+    torch.cuda.synchronize()
+    predict_ms = (time.perf_counter() - t0) * 1e3 / count
+    zero, learned, fallback = [], [], 0
+    for i in range(count):
+        z = ws.steps_to_tolerance(rho[i], n, tol)
+        w = ws.steps_to_tolerance(rho[i], n, tol, start=(phi[i], pd[i]))
+        zero.append(z[0])
+        if w[1] >= z[1]:
+            fallback += 1
+            learned.append(z[0] + 4)
+        else:
+            learned.append(w[0] + feats.coarse_cost_fine_steps)
+    mz, ml = float(np.median(zero)), float(np.median(learned))
+    return {"grid": n, "densities": count, "seeds": f"{seeds[0]}..{seeds[-1]}", "tol_Rb": tol,
+            "steps_zero_median": mz, "steps_learned_median": round(ml, 2), "ratio": round(mz / ml, 3),
+            "fallback": fallback, "coarse_cost_fine_steps": feats.coarse_cost_fine_steps,
+            "predict_ms_per_density": round(predict_ms, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +170,7 @@ def main():
     ap.add_argument("--tblock", type=int, default=0, help="substeps per fused launch (0 = autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched measurement")
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the steps-to-1e-4 warm-start measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (for scaling HBM counters)")
     args = ap.parse_args()
@@ -252,6 +294,10 @@ def main():
         log("[bench] batched: 64 uneven grids, 500 substeps")
         line["batched"] = run_batched(dev)
         log(f"[bench]   {line['batched']}")
+    if not args.no_warmstart:
+        log("[bench] warm start: steps to R_b < 1e-4 at 128^3, zero vs learned")
+        line["warm_start"] = run_warmstart(dev)
+        log(f"[bench]   {line['warm_start']}")
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle, one hydro step)")
         rho0 = workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * W), dev, torch.float32)

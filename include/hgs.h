@@ -208,6 +208,23 @@ hgs_status hgs_hydro_step(hgs_ctx* ctx, const void* rho, const void* cs, const v
  * current potential (FP64), rho device (nz,ny,nx) in the storage dtype. */
 hgs_status hgs_energy(hgs_ctx* ctx, const void* rho, double* w);
 
+/* ---- Extended gravity-only grid --------------------------------------------
+ * Sec. 4 proposes solving the wave equation on a grid wider than the region of
+ * the hydrodynamics, the extension close to vacuum, so that a local (Robin)
+ * boundary sits far from the matter at little cost.  A context built for the
+ * wider grid ((nx + 2 ext) x (ny + 2 ext) x (nz + 2 ext) cells, x0 moved out
+ * by ext dx) does this; these two calls move compact fields between the
+ * hydrodynamics region (nz, ny, nx) and the wider grid, both device arrays of
+ * the given dtype, enqueued on stream.
+ * hgs_embed: outer = inner in the centre, 0 in the extension (every outer
+ *   cell written).  hgs_extract: inner = the centre of outer.
+ * HGS_ERR_ARG for NULL pointers, sizes outside 1..8192 (or a wider grid beyond
+ * 8192 cells along an axis), ext < 0 or a bad dtype. */
+hgs_status hgs_embed(const void* inner, int32_t nx, int32_t ny, int32_t nz, int32_t ext, void* outer, int32_t dtype,
+                     void* stream);
+hgs_status hgs_extract(const void* outer, int32_t nx, int32_t ny, int32_t nz, int32_t ext, void* inner, int32_t dtype,
+                       void* stream);
+
 /* Bitwise copy of the raw two-level state (phi^n, phi^{n-1} interiors, device
  * (nz,ny,nx) buffers) and the previous step size, for checkpoint/resume. */
 hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev);

@@ -866,6 +866,53 @@ hgs_status hgs_energy(hgs_ctx* ctx, const void* rho, double* w) {
     return read_out(ctx, w, 1, "hgs_energy");
 }
 
+static hgs_status ext_check(const void* a, const void* b, int32_t nx, int32_t ny, int32_t nz, int32_t ext,
+                            int32_t dtype) {
+    if (!a || !b) return fail(nullptr, HGS_ERR_ARG, "field pointers must be non-NULL");
+    if (nx < 1 || ny < 1 || nz < 1 || ext < 0 || nx > kMaxN || ny > kMaxN || nz > kMaxN || ext > kMaxN)
+        return fail(nullptr, HGS_ERR_ARG, "need 1 <= nx, ny, nz <= 8192 and 0 <= ext <= 8192");
+    if ((int64_t)nx + 2 * (int64_t)ext > kMaxN || (int64_t)ny + 2 * (int64_t)ext > kMaxN ||
+        (int64_t)nz + 2 * (int64_t)ext > kMaxN)
+        return fail(nullptr, HGS_ERR_ARG, "extended grid larger than 8192 cells along an axis");
+    if (dtype != HGS_F32 && dtype != HGS_F64) return fail(nullptr, HGS_ERR_ARG, "dtype must be HGS_F32 or HGS_F64");
+    return HGS_OK;
+}
+
+hgs_status hgs_embed(const void* inner, int32_t nx, int32_t ny, int32_t nz, int32_t ext, void* outer, int32_t dtype,
+                     void* stream) {
+    hgs_status s = ext_check(inner, outer, nx, ny, nz, ext, dtype);
+    if (s != HGS_OK) return s;
+    (void)hipGetLastError();
+    const int64_t n = ((int64_t)nx + 2 * ext) * ((int64_t)ny + 2 * ext) * ((int64_t)nz + 2 * ext);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == HGS_F32)
+        hipLaunchKernelGGL(k_embed<float>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const float*>(inner), nx,
+                           ny, nz, ext, static_cast<float*>(outer));
+    else
+        hipLaunchKernelGGL(k_embed<double>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const double*>(inner),
+                           nx, ny, nz, ext, static_cast<double*>(outer));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HGS_OK : fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_embed: ") + hipGetErrorString(e));
+}
+
+hgs_status hgs_extract(const void* outer, int32_t nx, int32_t ny, int32_t nz, int32_t ext, void* inner, int32_t dtype,
+                       void* stream) {
+    hgs_status s = ext_check(outer, inner, nx, ny, nz, ext, dtype);
+    if (s != HGS_OK) return s;
+    (void)hipGetLastError();
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == HGS_F32)
+        hipLaunchKernelGGL(k_extract<float>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const float*>(outer), nx,
+                           ny, nz, ext, static_cast<float*>(inner));
+    else
+        hipLaunchKernelGGL(k_extract<double>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const double*>(outer),
+                           nx, ny, nz, ext, static_cast<double*>(inner));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HGS_OK
+                           : fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_extract: ") + hipGetErrorString(e));
+}
+
 hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev) {
     if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
     if (!phi_n || !phi_nm1 || !dt_prev) return fail(ctx, HGS_ERR_ARG, "phi_n, phi_nm1 and dt_prev must be non-NULL");

@@ -164,3 +164,38 @@ __global__ __launch_bounds__(256) void k_dot_partial(const S* __restrict__ rho, 
 }
 
 }  // namespace hgs
+
+namespace hgs {
+
+// Extended gravity-only grid (Sec. 4: solve the wave equation on a grid wider
+// than the hydrodynamics region, the extension taken as vacuum).  Compact
+// fields: inner (nz, ny, nx) <-> outer (nz + 2e, ny + 2e, nx + 2e).
+// k_embed writes every outer cell (inner values in the centre, 0 around).
+template <typename S>
+__global__ __launch_bounds__(256) void k_embed(const S* __restrict__ inner, int nx, int ny, int nz, int e,
+                                               S* __restrict__ outer) {
+    const int ox = nx + 2 * e, oy = ny + 2 * e, oz = nz + 2 * e;
+    const int64_t total = (int64_t)ox * oy * oz;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % ox) - e;
+        const int j = (int)((t / ox) % oy) - e;
+        const int k = (int)(t / ((int64_t)ox * oy)) - e;
+        const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+        outer[t] = in ? inner[((int64_t)k * ny + j) * nx + i] : (S)0;
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_extract(const S* __restrict__ outer, int nx, int ny, int nz, int e,
+                                                 S* __restrict__ inner) {
+    const int ox = nx + 2 * e, oy = ny + 2 * e;
+    const int64_t total = (int64_t)nx * ny * nz;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % nx);
+        const int j = (int)((t / nx) % ny);
+        const int k = (int)(t / ((int64_t)nx * ny));
+        inner[t] = outer[((int64_t)(k + e) * oy + (j + e)) * ox + (i + e)];
+    }
+}
+
+}  // namespace hgs

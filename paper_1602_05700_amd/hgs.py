@@ -68,6 +68,8 @@ _SIGS = {
     "hgs_max_signal_speed": (_i32, [_vp, _vp, _vp, _vp, _vp, _dp]),
     "hgs_hydro_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _dbl, _dp, ctypes.POINTER(_i32), _dp]),
     "hgs_energy": (_i32, [_vp, _vp, _dp]),
+    "hgs_embed": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
+    "hgs_extract": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
     "hgs_save_raw": (_i32, [_vp, _vp, _vp, _dp]),
     "hgs_load_raw": (_i32, [_vp, _vp, _vp, _dbl]),
     "hgs_set_tblock": (_i32, [_vp, _i32]),
@@ -341,6 +343,65 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class ExtendedSolver:
+    """A solver on a grid wider than the hydrodynamics region by `ext` cells on
+    every side, the extension treated as vacuum (Sec. 4: a cheap way to move a
+    local boundary away from the matter).  rho, phi and g are exchanged on the
+    hydrodynamics region (nz, ny, nx) only; hgs_embed / hgs_extract move them."""
+
+    def __init__(self, shape, ext: int, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, bc: str = "outgoing",
+                 **kw):
+        import torch
+
+        nz, ny, nx = (shape, shape, shape) if np.isscalar(shape) else shape
+        dx = float(dx) if dx is not None else 2.0 / nx
+        self.inner = (nz, ny, nx)
+        self.ext = int(ext)
+        e = self.ext
+        self.solver = Solver((nz + 2 * e, ny + 2 * e, nx + 2 * e),
+                             x0=tuple(float(v) - e * dx for v in x0), dx=dx, bc=bc, **kw)
+        s = self.solver
+        self.dtype, self.device, self.stream = s.dtype, s.device, s.stream
+        self._code = HGS_F32 if s.dtype == torch.float32 else HGS_F64
+        self._rho = torch.empty(s.shape, dtype=s.dtype, device=s.device)
+
+    def _in(self, t):
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != self.inner:
+            raise ValueError(f"expected a contiguous {self.dtype} tensor of shape {self.inner} on {self.device}")
+        return t
+
+    def embed(self, inner, outer) -> None:
+        nz, ny, nx = self.inner
+        _check(_lib.hgs_embed(self._in(inner).data_ptr(), nx, ny, nz, self.ext, outer.data_ptr(), self._code,
+                              self.stream.cuda_stream))
+
+    def extract(self, outer, inner=None):
+        nz, ny, nx = self.inner
+        out = self.solver.torch.empty(self.inner, dtype=self.dtype, device=self.device) if inner is None else inner
+        _check(_lib.hgs_extract(outer.data_ptr(), nx, ny, nz, self.ext, self._in(out).data_ptr(), self._code,
+                                self.stream.cuda_stream))
+        return out
+
+    def step(self, rho, c_g: float, dt: float, nsub: int) -> None:
+        self.embed(rho, self._rho)
+        self.solver.step(self._rho, c_g, dt, nsub)
+
+    def potential(self, with_phidot: bool = True):
+        phi, pd = self.solver.potential(with_phidot)
+        return self.extract(phi), (self.extract(pd) if pd is not None else None)
+
+    def accel(self):
+        return tuple(self.extract(g) for g in self.solver.accel())
+
+    def residual(self, rho) -> np.ndarray:
+        """Residual over the whole wider grid (rho embedded)."""
+        self.embed(rho, self._rho)
+        return self.solver.residual(self._rho)
+
+    def close(self) -> None:
+        self.solver.close()
 
 
 def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32", lmax: int = 4,

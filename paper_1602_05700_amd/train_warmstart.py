@@ -208,6 +208,7 @@ def main():
         for w in [float(v) for v in args.lap_w.split(",")]:
             net = ws.Net.create(dev, seed=0)
             net.out_scale = out_scale
+            net.coarse_steps = args.coarse_steps
             info = train(net, P, tgt, args, w, dev, log_prefix=f" w={w:g}")
             vs = summarise(evaluate(net, val, val_seeds, n, feats, args, dev, controls=False, tag=f"val w={w:g}"),
                            cc)

@@ -22,6 +22,7 @@ per coarse substep and is reported in fine-step equivalents.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -32,6 +33,9 @@ NC = hgs.NN_CHANNELS
 N_LAYERS = 4
 IN_CH = 3   # rho, coarse phi, its residual of the discrete Poisson equation
 OUT_CH = 2  # phi correction, dphi/dt
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_weights.npz")
 
 
 def lambda_min(n: int, dx: float) -> float:
@@ -58,6 +62,7 @@ class Net:
     vb: list = field(default_factory=list)
     t: int = 0
     out_scale: float = 1.0
+    coarse_steps: int = 200  # length of the coarse solve the network was trained with
 
     @staticmethod
     def create(device, seed: int = 0) -> "Net":
@@ -83,7 +88,7 @@ class Net:
         return net
 
     def state_dict(self) -> dict:
-        d = {"out_scale": np.array(self.out_scale)}
+        d = {"out_scale": np.array(self.out_scale), "coarse_steps": np.array(self.coarse_steps)}
         for i in range(N_LAYERS):
             d[f"w{i}"] = self.w[i].cpu().numpy()
             d[f"b{i}"] = self.b[i].cpu().numpy()
@@ -93,6 +98,8 @@ class Net:
         import torch
 
         self.out_scale = float(d["out_scale"])
+        if "coarse_steps" in d:
+            self.coarse_steps = int(d["coarse_steps"])
         for i in range(N_LAYERS):
             self.w[i] = torch.from_numpy(np.asarray(d[f"w{i}"], dtype=np.float32)).to(self.device)
             self.b[i] = torch.from_numpy(np.asarray(d[f"b{i}"], dtype=np.float32)).to(self.device)

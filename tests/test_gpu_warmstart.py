@@ -89,3 +89,33 @@ def test_small_end_to_end(gpu_lib):
     assert phi.shape == (1, n, n, n) and torch.isfinite(phi).all() and torch.isfinite(pd).all()
     steps, r0, rb = ws.steps_to_tolerance(rho[0], n, 1e-4, start=(phi[0], pd[0]))
     assert rb < 1e-4 and steps < 4000
+
+
+def test_committed_weights_cut_steps_threefold(gpu_lib):
+    """The trained network shipped with the package, on held-out 128^3
+    densities: substeps of the damped FP32 solver to R_b < 1e-4 from its warm
+    start (coarse solve counted in fine-substep equivalents) against the zero
+    start.  The median gain must reach 3x with no fallback to the zero start."""
+    import os
+
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import warmstart as ws
+
+    assert os.path.exists(ws.WEIGHTS)
+    n = 128
+    net = ws.Net.load(ws.WEIGHTS, "cuda")
+    feats = ws.Features(n, "cuda", coarse_steps=net.coarse_steps)
+    seeds = list(range(20000, 20006))
+    rho = torch.stack([workloads.blob_density_torch(n, workloads.warmstart_blobs(s), "cuda", torch.float32)
+                       for s in seeds])
+    planar, phi2, scale = feats.inputs(rho)
+    phi, pd = ws.predict_fine(net, planar, phi2, scale, n)
+    ratios = []
+    for i in range(len(seeds)):
+        zero = ws.steps_to_tolerance(rho[i], n, 1e-4)
+        warm = ws.steps_to_tolerance(rho[i], n, 1e-4, start=(phi[i], pd[i]))
+        assert warm[1] < zero[1] and warm[2] < 1e-4
+        ratios.append(zero[0] / (warm[0] + feats.coarse_cost_fine_steps))
+    assert np.median(ratios) >= 3.0, ratios
