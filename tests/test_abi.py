@@ -154,3 +154,14 @@ def test_local_boundaries_host_checks():
     cfgs = (hgs.Config * 2)(hgs.make_config(16), hgs.make_config(16, bc="robin"))
     assert L.hgs_workspace_bytes_batch(cfgs, 2, ctypes.byref(n)) == hgs.HGS_ERR_ARG
     assert b"frozen" in L.hgs_last_error(None)
+
+
+def test_embed_extract_host_checks():
+    L = hgs.library()
+    a = ctypes.c_void_p(16)  # never dereferenced: every case below fails validation first
+    assert L.hgs_embed(None, 4, 4, 4, 2, a, hgs.HGS_F32, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_embed(a, 4, 4, 4, -1, a, hgs.HGS_F32, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_embed(a, 4, 0, 4, 1, a, hgs.HGS_F32, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_embed(a, 4, 4, 4, 1, a, 9, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_extract(a, 8000, 4, 4, 200, a, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_extract(a, 4, 4, 4, 1, None, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
