@@ -12,7 +12,7 @@
  * (Sec. 2 and Sec. 4, Table I model aD05) or a caller-supplied one; the
  * gravitational acceleration is g = -grad phi.
  *
- * Discretisation (the paper only says "simple discretization", Sec. 2):
+ * Discretisation (Sec. 2 leaves it unspecified):
  *   cell-centred uniform grid of nx*ny*nz cubic cells of size dx; cell (i,j,k)
  *   centre = (x0 + (i+1/2) dx, y0 + (j+1/2) dx, z0 + (k+1/2) dx);
  *   7-point Laplacian L_h with one layer of ghost cells outside each face;
@@ -21,7 +21,11 @@
  *   the discrete Poisson solution -- unchanged and lets a zero start relax):
  *     phi^{n+1} = [2 phi^n - (1 - a) phi^{n-1} + c^2 dt^2 (L_h phi^n - 4 pi G rho)] / (1 + a),
  *     a = eta dt / 2.
- *   Arithmetic is FP64 for every storage dtype; only stored fields are rounded.
+ *   FP64 storage: FP64 arithmetic.  FP32 storage: the substep is evaluated in
+ *   FP32 in increment form, phi^{n+1} = phi^n + [(1-a)(phi^n - phi^{n-1}) +
+ *   kk sum(nb - phi^n) - c^2 dt^2 4 pi G rho]/(1+a), whose differences of
+ *   nearby FP32 values are exact, so the stored state keeps the accuracy of
+ *   FP64 arithmetic; moments, boundary values, gradient and norms are FP64.
  *
  * Conventions for every call below.
  *   - 3D field buffers passed by the caller (rho, phi, phidot, gx, gy, gz, the

@@ -27,8 +27,8 @@ arXiv:1602.05700), and what pins it (tests/test_oracle_pins.py):
   convergence toward the closed-form Gaussian potential.
 * ``orc_substeps_local`` / ``orc_local_ghosts`` / ``orc_residual_local`` --
   local outer boundaries whose ghosts follow the interior every substep: the
-  Robin condition the paper uses by default ("equivalent to assuming monopole
-  gravity", Sec. 4) read as r_g phi_g = r_i phi_i; its radiative form
+  Robin condition the paper uses by default (a monopole far field, Sec. 4)
+  read as r_g phi_g = r_i phi_i; its radiative form
   d(r phi)/dt + c d(r phi)/dr = 0 (box scheme); periodic with the domain-mean
   density subtracted from the source (Sec. 4).  Pinned by
   (tests/test_oracle_bc.py): exactness on -G M / r, a sparse direct solve of

@@ -18,7 +18,7 @@
  *
  * Functions:
  *   orc_moments    multipole moments of rho (Sec. 2 / Sec. 4: Dirichlet
- *                  boundary "by multipole expansion"), complex orthonormal
+ *                  boundary from a multipole expansion), complex orthonormal
  *                  Y_lm written out from the textbook definition.
  *   orc_boundary   ghost values phi_b = -G sum_lm 4pi/(2l+1) Q_lm Y_lm / r^(l+1).
  *   orc_substeps   explicit leapfrog time stepping of Eq. (2), optionally with a
@@ -321,13 +321,13 @@ void orc_substeps(int nx, int ny, int nz, double dx, double* phi_n, double* phi_
  * Local outer boundaries (the ghost layer follows the interior every substep).
  *
  * 2 = Robin: the paper's default outer boundary, a Robin condition that
- *     amounts to assuming monopole gravity (Sec. 2, Sec. 4).  Read as the
+ *     is equivalent to a monopole far field (Sec. 2, Sec. 4).  Read as the
  *     monopole fall-off d(r phi)/dr = 0 between a ghost and the interior cell
  *     next to it:  r_g phi_g = r_i phi_i,  r measured from the expansion
  *     centre.  Exact for any potential -G M / r about that centre.
  * 3 = outgoing: the radiative form of the same condition, an outgoing
  *     spherical wave  d(r phi)/dt + c d(r phi)/dr = 0, which lets errors
- *     "propagate away out of the boundaries" (Sec. 4).  With u = r phi and the
+ *     leave the domain through the boundary (Sec. 4).  With u = r phi and the
  *     radial derivative taken along the face normal, d/dr = d/dn / cos(theta),
  *     cos(theta) = n . x_f / |x_f| at the midpoint x_f of ghost and neighbour,
  *     the condition is discretised by the box scheme centred on that midpoint

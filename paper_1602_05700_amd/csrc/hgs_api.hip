@@ -221,6 +221,9 @@ StepCoef step_coef(const hgs_ctx* c, double cg, double dt) {
     s.c1 = kk * inv;
     s.cm = -(1.0 - a) * inv;
     s.cs = -c2dt2 * 4.0 * M_PI * c->cfg.G * inv;
+    s.fo = (float)((1.0 - a) * inv);
+    s.fl = (float)s.c1;
+    s.fs = (float)s.cs;
     return s;
 }
 

@@ -2,7 +2,7 @@
 // substep, instead of being frozen over a hydrodynamical step.
 //
 //   Robin    -- the paper's default outer boundary, a Robin condition that
-//               amounts to assuming monopole gravity (Sec. 2, Sec. 4), read
+//               is equivalent to a monopole far field (Sec. 2, Sec. 4), read
 //               as the monopole fall-off d(r phi)/dr = 0 between a ghost and
 //               its interior neighbour: r_g phi_g = r_i phi_i (r from the
 //               expansion centre).  Exact for -G M / r.

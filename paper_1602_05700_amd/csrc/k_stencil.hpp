@@ -38,15 +38,15 @@ __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict_
     const int64_t sxy = (int64_t)L.nx * L.ny;
     const S* pr = rho + (int64_t)k0 * sxy + (int64_t)j * L.nx + i;
     const double rb = rbar ? *rbar : 0.0;
-    double zm = ld(pc - plane);
-    double z0 = ld(pc);
+    S zm = pc[-plane];
+    S z0 = pc[0];
     for (int k = k0; k < k1; ++k) {
-        const double zp = ld(pc + plane);
-        const double xm = ld(pc - 1), xp = ld(pc + 1);
-        const double ym = ld(pc - pitch), yp = ld(pc + pitch);
-        const double o = ld(po);
-        const double r = ld(pr) - rb;
-        *po = (S)leapfrog_update(c, z0, xm, xp, ym, yp, zm, zp, o, r);
+        const S zp = pc[plane];
+        const S xm = pc[-1], xp = pc[1];
+        const S ym = pc[-pitch], yp = pc[pitch];
+        const S o = *po;
+        const S r = source(*pr, rb);
+        *po = (S)update(c, z0, xm, xp, ym, yp, zm, zp, o, r);
         zm = z0;
         z0 = zp;
         pc += plane;
@@ -201,12 +201,11 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
         VT out;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
-            const double xm = n > 0 ? (double)V::get(z0, n - 1) : (double)left;
-            const double xp = n < N - 1 ? (double)V::get(z0, n + 1) : (double)right;
-            const double v = leapfrog_update(c, (double)V::get(z0, n), xm, xp, (double)V::get(ym, n),
-                                             (double)V::get(yp, n), (double)V::get(zm, n), (double)V::get(zp, n),
-                                             (double)V::get(o, n), (double)V::get(r, n) - rb);
-            V::set(out, n, (S)v);
+            const S xm = n > 0 ? (S)V::get(z0, n - 1) : left;
+            const S xp = n < N - 1 ? (S)V::get(z0, n + 1) : right;
+            const S v = (S)update(c, (S)V::get(z0, n), xm, xp, (S)V::get(ym, n), (S)V::get(yp, n),
+                                  (S)V::get(zm, n), (S)V::get(zp, n), (S)V::get(o, n), source((S)V::get(r, n), rb));
+            V::set(out, n, v);
         }
         if (g.active) *reinterpret_cast<VT*>(po) = out;
         zm = z0;

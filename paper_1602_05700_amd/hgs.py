@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhgs.so")
+LIB_PATH = os.environ.get("HGS_LIBRARY") or os.path.join(_HERE, "libhgs.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
