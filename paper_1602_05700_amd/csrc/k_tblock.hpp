@@ -285,13 +285,14 @@ inline TBlockDims tblock_dims(const Layout& L, int slots) {
 
 // Tile shape (R rows per thread, W waves per workgroup) per storage type and
 // depth, chosen by measurement on MI355X at 512^3 and bounded by registers:
-// every level keeps three planes per cell in registers.  FP32 at T = 4:
-// R = 4 (extended tile 64 x 32, 66% of the computed cells kept) fits in 223
-// VGPRs; R = 5 spills.
+// every level keeps three planes per cell in registers.  FP32: 16 waves of
+// 2 rows (extended tile 64 x 32; 112 VGPRs at T = 4, so the 16 waves fit one
+// CU): as fast as 8 waves of 4 rows at T = 4 and 6-11% faster at T = 2, 3.
+// FP64: 8 waves of 2 rows.
 template <typename S, int T>
 struct TBConfig {
-    static constexpr int R = sizeof(S) == 4 ? (T == 3 ? 3 : 4) : 2;
-    static constexpr int W = 8;
+    static constexpr int R = 2;
+    static constexpr int W = sizeof(S) == 4 ? 16 : 8;
 };
 
 template <typename S, int T>
