@@ -124,12 +124,15 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
     blob mixtures (held-out seeds 20000..), from the zero start and from the
     learned start with the committed weights (zero start as fallback); the
     coarse solve that feeds the network is counted in fine-substep
-    equivalents."""
+    equivalents.  Wall time as well: one density's prediction (restriction,
+    coarse solve, features, network, prolongation) plus the median learned
+    substep count, against the median zero-start count, each timed with events
+    as one uninterrupted sequence of launches."""
     import numpy as np
     import torch
 
     import workloads
-    from paper_1602_05700_amd import warmstart as ws
+    from paper_1602_05700_amd import hgs, warmstart as ws
 
     if not os.path.exists(ws.WEIGHTS):
         return {"skipped": "no trained weights in the package"}
@@ -138,11 +141,8 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
     seeds = list(range(20000, 20000 + count))
     rho = torch.stack([workloads.blob_density_torch(n, workloads.warmstart_blobs(s), dev, torch.float32)
                        for s in seeds])
-    t0 = time.perf_counter()
     planar, phi2, scale = feats.inputs(rho)
     phi, pd = ws.predict_fine(net, planar, phi2, scale, n)
-    torch.cuda.synchronize()
-    predict_ms = (time.perf_counter() - t0) * 1e3 / count
     zero, learned, fallback = [], [], 0
     for i in range(count):
         z = ws.steps_to_tolerance(rho[i], n, tol)
@@ -154,10 +154,48 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
         else:
             learned.append(w[0] + feats.coarse_cost_fine_steps)
     mz, ml = float(np.median(zero)), float(np.median(learned))
+
+    # wall time, density 0: prediction for one density, then the substeps
+    dx = 2.0 / n
+    dt = 0.4 * dx
+    eta = ws.eta_critical(n, dx)
+    r0 = rho[0].contiguous()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def solve(start, nsub):
+        s = hgs.Solver(n, storage="f32", lmax=4, eta=eta, device=dev)
+        if start is not None:
+            s.set_state(start[0], start[1], dt)
+        return s
+
+    for rep in range(2):  # first pass warms up
+        torch.cuda.synchronize()
+        e[0].record()
+        p_in, p_c, p_s = feats.inputs(r0[None])
+        f_phi, f_pd = ws.predict_fine(net, p_in, p_c, p_s, n)
+        e[1].record()
+        s = solve((f_phi[0].contiguous(), f_pd[0].contiguous()), 0)
+        n_l = int(round(np.median([v - feats.coarse_cost_fine_steps for v in learned])))
+        e[2].record()
+        s.step(r0, 1.0, dt, n_l)
+        e[3].record()
+        torch.cuda.synchronize()
+        s.close()
+    predict_ms = e[0].elapsed_time(e[1])
+    learned_ms = predict_ms + e[2].elapsed_time(e[3])
+    s = solve(None, 0)
+    torch.cuda.synchronize()
+    e[0].record()
+    s.step(r0, 1.0, dt, int(mz))
+    e[1].record()
+    torch.cuda.synchronize()
+    zero_ms = e[0].elapsed_time(e[1])
+    s.close()
     return {"grid": n, "densities": count, "seeds": f"{seeds[0]}..{seeds[-1]}", "tol_Rb": tol,
             "steps_zero_median": mz, "steps_learned_median": round(ml, 2), "ratio": round(mz / ml, 3),
             "fallback": fallback, "coarse_cost_fine_steps": feats.coarse_cost_fine_steps,
-            "predict_ms_per_density": round(predict_ms, 2)}
+            "wall_ms_zero": round(zero_ms, 3), "wall_ms_learned": round(learned_ms, 3),
+            "wall_ms_predict": round(predict_ms, 3), "wall_ratio": round(zero_ms / learned_ms, 3)}
 
 
 def main():

@@ -327,7 +327,8 @@ hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32
                          int32_t nx, int32_t ch, float w, float* scratch, uint16_t* grad, double* loss_dev,
                          double* partials, void* stream);
 /* Warm-start inputs and outputs (FP32, device).
- * hgs_nn_maxabs: out[b] = max |x[b][v]| over nvox values (one per sample).
+ * hgs_nn_maxabs: out[b] = max |x[b][v]| over nvox values (one per sample);
+ *   scratch: B * HGS_NN_MAXABS_CHUNKS floats of device memory.
  * hgs_nn_features: planar inputs out[B][3][nz][ny][nx] from rho and a coarse
  *   potential phi ([B][nz][ny][nx]) on a grid of spacing h, c = 4 pi G h^2:
  *   rho / s, phi / s and the potential's residual of the discrete Poisson
@@ -337,7 +338,8 @@ hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32
  * hgs_nn_compose: phi = phi_c + y[..., 0] s / out_scale and (phidot nullable)
  *   phidot = y[..., 1] s / out_scale from the last layer's channels-last FP32
  *   output y ([B][nvox][16]); inv_out_scale = 1 / out_scale. */
-hgs_status hgs_nn_maxabs(const float* x, int32_t B, int64_t nvox, float* out, void* stream);
+#define HGS_NN_MAXABS_CHUNKS 64
+hgs_status hgs_nn_maxabs(const float* x, int32_t B, int64_t nvox, float* out, float* scratch, void* stream);
 hgs_status hgs_nn_features(const float* rho, const float* phi, const float* scale, int32_t B, int32_t nz, int32_t ny,
                            int32_t nx, double c, float* out, void* stream);
 hgs_status hgs_nn_compose(const float* phi_c, const float* y, const float* scale, int32_t B, int64_t nvox,

@@ -984,7 +984,8 @@ struct BatchPlan {
 };
 
 template <typename S>
-void batch_items(const std::vector<Layout>& Ls, int T, std::vector<WorkItem>& tb, std::vector<WorkItem>& st) {
+void batch_items(const std::vector<Layout>& Ls, int T, int zchunk, std::vector<WorkItem>& tb,
+                 std::vector<WorkItem>& st) {
     tb.clear();
     st.clear();
     std::vector<std::pair<int64_t, WorkItem>> a, b;
@@ -998,7 +999,7 @@ void batch_items(const std::vector<Layout>& Ls, int T, std::vector<WorkItem>& tb
                 default: IY = TBConfig<S, 4>::W * TBConfig<S, 4>::R - 8; break;
             }
             const int tx = (L.nx + IX - 1) / IX, ty = (L.ny + IY - 1) / IY;
-            const int zc = std::min(L.nz, 64);
+            const int zc = std::min(L.nz, zchunk);
             for (int z = 0; z < L.nz; z += zc)
                 for (int y = 0; y < ty; ++y)
                     for (int x = 0; x < tx; ++x) {
@@ -1025,6 +1026,36 @@ void batch_items(const std::vector<Layout>& Ls, int T, std::vector<WorkItem>& tb
     for (auto& p : a) tb.push_back(p.second);
     for (auto& p : b) st.push_back(p.second);
 }
+
+// z-chunk of the fused work items: each item costs (chunk + 2T) pipeline
+// steps; the launch's min(items, slots) workgroups take items in cost order,
+// strided.  Pick the chunk whose busiest workgroup has the fewest steps (ties
+// to the longer chunk, which recomputes fewer halo planes).  Small batches
+// then split z finely instead of leaving most CUs idle.
+template <typename S>
+int batch_zchunk(const std::vector<Layout>& Ls, int T, int slots) {
+    static const int cand[] = {64, 48, 32, 24, 16, 12, 8, 6, 4};
+    int best = 64;
+    int64_t best_span = -1;
+    std::vector<WorkItem> tb, st;
+    for (int zc : cand) {
+        if (zc < 2 * T) continue;  // as the single-grid launcher: at least 2T planes per chunk
+        batch_items<S>(Ls, T, zc, tb, st);
+        const int nb = std::max(1, std::min((int)tb.size(), slots));
+        std::vector<int64_t> load(nb, 0);
+        for (size_t j = 0; j < tb.size(); ++j) load[j % nb] += tb[j].k1 - tb[j].k0 + 2 * T;
+        const int64_t span = *std::max_element(load.begin(), load.end());
+        if (best_span < 0 || span < best_span) {
+            best_span = span;
+            best = zc;
+        }
+    }
+    return best;
+}
+
+// workgroup slots the batch planner assumes (one fused workgroup per CU of
+// an MI355X); planning runs on the host, also without a device
+constexpr int kPlanSlots = 256;
 
 hgs_status batch_plan(const hgs_config* cfgs, int32_t n, BatchPlan& p, std::string& why) {
     if (!cfgs || n < 1 || n > 4096) {
@@ -1063,9 +1094,9 @@ hgs_status batch_plan(const hgs_config* cfgs, int32_t n, BatchPlan& p, std::stri
     }
     const int T = default_tblock(&cfgs[0]);
     if (cfgs[0].storage == HGS_F64)
-        batch_items<double>(Ls, T, p.tb_items, p.st_items);
+        batch_items<double>(Ls, T, batch_zchunk<double>(Ls, T, kPlanSlots), p.tb_items, p.st_items);
     else
-        batch_items<float>(Ls, T, p.tb_items, p.st_items);
+        batch_items<float>(Ls, T, batch_zchunk<float>(Ls, T, kPlanSlots), p.tb_items, p.st_items);
     const size_t dsz = cfgs[0].storage == HGS_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
     p.desc_off = off;
     off = align_up(off + dsz * n, kAlign);

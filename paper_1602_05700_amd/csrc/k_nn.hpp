@@ -30,6 +30,14 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// tanh for bf16 outputs: (1 - e) / (1 + e) with e = exp(-2|x|), sign restored,
+// the quotient by the hardware reciprocal; the error (a few 1e-7 absolute) is
+// far below one bf16 rounding step
+__device__ __forceinline__ float tanh_bf(float x) {
+    const float e = __expf(-2.f * fabsf(x));
+    return copysignf((1.f - e) * __builtin_amdgcn_rcpf(1.f + e), x);
+}
+
 enum ConvMode {
     CONV_F32 = 0,         // out (FP32) = conv + bias
     CONV_TANH_BF16 = 1,   // out (bf16) = tanh(conv + bias)
@@ -80,7 +88,7 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
         for (int i = 0; i < 4; ++i) {
             float s = acc[i];
             if (mode == CONV_TANH_BF16) {
-                s = tanhf(s + (bias ? bias[4 * kq + i] : 0.f));
+                s = tanh_bf(s + (bias ? bias[4 * kq + i] : 0.f));
             } else if (mode == CONV_DTANH_BF16) {
                 const float yv = bf2f((uint16_t)ax[i]);
                 s = s * (1.f - yv * yv);
@@ -90,6 +98,138 @@ __global__ __launch_bounds__(256) void k_conv3d(const uint16_t* __restrict__ in,
             v[i] = (short)f2bf(s);
         }
         *reinterpret_cast<bf16x4*>(static_cast<uint16_t*>(out) + o) = v;
+    }
+}
+
+// The same convolution with the input and the weights staged in LDS.  A
+// workgroup of four waves computes four consecutive output rows (y0..y0+3) of
+// one z plane over the whole x extent X = 16 SEGS.  It first copies the 27
+// weight matrices and the 3 x 6 x (X+2) input voxels those rows read (z-1..z+1,
+// y0-1..y0+4, x -1..X; zero outside the grid) into LDS with 16-byte loads,
+// then each wave runs its row's 27 taps x SEGS MFMAs with both fragments read
+// from LDS (8 bytes per lane; a wave's B reads are 512 contiguous bytes).
+// SEGS is a template parameter so that the tap loop has no branches: with a
+// run-time segment count every guarded MFMA made the compiler shuffle all
+// accumulators through copies.  X <= CONV_LDS_MAXX keeps tile and weights
+// within 64 KB.
+//
+// LDS swizzle: a voxel (or a weight row) is 32 bytes, two 16-byte halves of
+// 8 channels.  Where bit 3 of the voxel's x index (of the weight row's index)
+// is set the halves are stored swapped, so the 8-byte reads of 32 lanes, which
+// cover 16 consecutive voxels, fall on 64 distinct banks instead of two lanes
+// per bank.
+constexpr int CONV_LDS_MAXX = 64;
+template <int SEGS>
+__global__ __launch_bounds__(256) void k_conv3d_lds(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
+                                                    const float* __restrict__ bias, int B, int Z, int Y, int mode,
+                                                    const uint16_t* __restrict__ aux, void* __restrict__ out) {
+    constexpr int X = 16 * SEGS;
+    constexpr int XE = X + 2;
+    __shared__ __align__(16) uint16_t tile[3][6][XE][NC];
+    __shared__ __align__(16) uint16_t wsh[27][NC][NC];
+    const int ybl = (Y + 3) / 4;
+    const int yb = blockIdx.x % ybl;
+    const int z = (blockIdx.x / ybl) % Z;
+    const int b = blockIdx.x / (ybl * Z);
+    const int y0 = yb * 4;
+    // stage: 2 halves of 8 channels (16 bytes) per voxel, then the weights.
+    // Every load of a thread is issued before its first LDS store, so the
+    // global latencies overlap instead of adding up.
+    constexpr int NHALF = 3 * 6 * XE * 2;
+    constexpr int NSTAGE = (NHALF + 255) / 256;
+    uint4 buf[NSTAGE];
+#pragma unroll
+    for (int i = 0; i < NSTAGE; ++i) {
+        const int h = threadIdx.x + i * 256;
+        buf[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (h < NHALF) {
+            const int v = h >> 1;
+            const int xe = v % XE;
+            const int xx = xe - 1, yy = y0 + (v / XE) % 6 - 1, zz = z + v / (XE * 6) - 1;
+            const int half = (h ^ (xe >> 3)) & 1;  // the swizzled half this slot holds
+            if (xx >= 0 && xx < X && yy >= 0 && yy < Y && zz >= 0 && zz < Z)
+                buf[i] = *reinterpret_cast<const uint4*>(in + ((((int64_t)b * Z + zz) * Y + yy) * X + xx) * NC +
+                                                         8 * half);
+        }
+    }
+    // the 27 x 16 x 16 weights: 864 16-byte pieces, at most four per thread
+    const uint4* wsrc = reinterpret_cast<const uint4*>(w);
+    constexpr int NWP = 27 * NC * NC / 8;
+    static_assert(NWP > 768 && NWP <= 1024, "weight staging expects four pieces per thread");
+    const int t0 = threadIdx.x;
+    // piece P = 2 (32 t + row) + half; slot P holds piece P ^ bit 3 of row
+    const int wsw = t0 ^ ((t0 >> 4) & 1);  // the same for t0 + 256 k
+    const uint4 wb0 = wsrc[wsw], wb1 = wsrc[wsw + 256], wb2 = wsrc[wsw + 512];
+    const uint4 wb3 = t0 + 768 < NWP ? wsrc[wsw + 768] : make_uint4(0u, 0u, 0u, 0u);
+    // the staged halves are consecutive 16-byte slots of tile in this order
+    uint4* tdst = reinterpret_cast<uint4*>(&tile[0][0][0][0]);
+#pragma unroll
+    for (int i = 0; i < NSTAGE; ++i) {
+        const int h = threadIdx.x + i * 256;
+        if (h < NHALF) tdst[h] = buf[i];
+    }
+    uint4* wdst = reinterpret_cast<uint4*>(&wsh[0][0][0]);
+    wdst[t0] = wb0;
+    wdst[t0 + 256] = wb1;
+    wdst[t0 + 512] = wb2;
+    if (t0 + 768 < NWP) wdst[t0 + 768] = wb3;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int y = y0 + wv;
+    if (y >= Y) return;  // after the only barrier; whole waves
+    const int col = lane & 15, kq = lane >> 4;
+    f32x4v acc[SEGS];
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) acc[s] = (f32x4v){0.f, 0.f, 0.f, 0.f};
+    // 4-channel group kq sits at group kq ^ 2 where the halves are swapped
+    const uint16_t* wbase = &wsh[0][col][4 * (kq ^ (2 * ((col >> 3) & 1)))];
+    const uint16_t* tb[3];  // per dx: x index col + dx (+ 16 s, which keeps bit 3)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+        tb[dx] = &tile[0][wv][col + dx][4 * (kq ^ (2 * (((col + dx) >> 3) & 1)))];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // offsets into the tile (0..2)
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(wbase + t * NC * NC);
+        bf16x4 bv[SEGS];
+#pragma unroll
+        for (int s = 0; s < SEGS; ++s)
+            bv[s] = *reinterpret_cast<const bf16x4*>(tb[dx] + ((dz * 6 + dy) * XE + s * 16) * NC);
+#pragma unroll
+        for (int s = 0; s < SEGS; ++s) acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv[s], acc[s], 0, 0, 0);
+    }
+    float bz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bz[i] = bias ? bias[4 * kq + i] : 0.f;
+#pragma unroll
+    for (int s = 0; s < SEGS; ++s) {
+        const int x = s * 16 + col;
+        const int64_t o = ((((int64_t)b * Z + z) * Y + y) * X + x) * NC + 4 * kq;
+        if (mode == CONV_F32) {
+            f32x4v v;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = acc[s][i] + bz[i];
+            *reinterpret_cast<f32x4v*>(static_cast<float*>(out) + o) = v;
+        } else {
+            bf16x4 v;
+            bf16x4 ax = {0, 0, 0, 0};
+            if (mode == CONV_DTANH_BF16) ax = *reinterpret_cast<const bf16x4*>(aux + o);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float sv = acc[s][i];
+                if (mode == CONV_TANH_BF16) {
+                    sv = tanh_bf(sv + bz[i]);
+                } else if (mode == CONV_DTANH_BF16) {
+                    const float yv = bf2f((uint16_t)ax[i]);
+                    sv = sv * (1.f - yv * yv);
+                } else {
+                    sv = sv + bz[i];
+                }
+                v[i] = (short)f2bf(sv);
+            }
+            *reinterpret_cast<bf16x4*>(static_cast<uint16_t*>(out) + o) = v;
+        }
     }
 }
 
@@ -107,10 +247,52 @@ __global__ void k_flip_weights(const uint16_t* __restrict__ w, uint16_t* __restr
 // transposed in LDS so that voxels become the MFMA k dimension.  Per-workgroup
 // partials are summed by k_wgrad_final in a fixed order.
 constexpr int WG_MAXX = 128;
+constexpr int WG_VPL = (WG_MAXX + 2 + 63) / 64;  // voxels per lane in a staged row
+// LDS row pitch of the transposed rows: 136 elements (68 banks of 4 bytes)
+// spreads the 16 rows a wave reads at once over distinct banks, and keeps
+// 4-element groups 8-byte aligned
+constexpr int WG_PITCH = WG_MAXX + 8;
+
+// One row of 16-channel voxels into registers (two 16-byte loads per voxel);
+// voxel slot j of this lane is x = lane + 64 j - off, zero outside [0, X) or
+// when the row is outside the grid.
+__device__ __forceinline__ void wg_load_row(const uint16_t* __restrict__ src, bool ok, int n, int off, int X,
+                                            int lane, uint4 (&r)[WG_VPL][2]) {
+#pragma unroll
+    for (int j = 0; j < WG_VPL; ++j) {
+        const int v = lane + 64 * j;
+        const int xx = v - off;
+        r[j][0] = r[j][1] = make_uint4(0u, 0u, 0u, 0u);
+        if (ok && v < n && xx >= 0 && xx < X) {
+            const uint4* p = reinterpret_cast<const uint4*>(src + (int64_t)xx * NC);
+            r[j][0] = p[0];
+            r[j][1] = p[1];
+        }
+    }
+}
+
+// Registers of wg_load_row into LDS transposed: dst[c * pitch + v] = channel c.
+__device__ __forceinline__ void wg_store_T(uint16_t* __restrict__ dst, int pitch, int n, int lane,
+                                           const uint4 (&r)[WG_VPL][2]) {
+#pragma unroll
+    for (int j = 0; j < WG_VPL; ++j) {
+        const int v = lane + 64 * j;
+        if (v < n) {
+            const uint32_t wds[8] = {r[j][0].x, r[j][0].y, r[j][0].z, r[j][0].w,
+                                     r[j][1].x, r[j][1].y, r[j][1].z, r[j][1].w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                dst[(2 * q) * pitch + v] = (uint16_t)(wds[q] & 0xffffu);
+                dst[(2 * q + 1) * pitch + v] = (uint16_t)(wds[q] >> 16);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_wgrad_partial(const uint16_t* __restrict__ a, const uint16_t* __restrict__ g,
                                                        int B, int Z, int Y, int X, float* __restrict__ partial) {
-    __shared__ uint16_t gT[4][NC][WG_MAXX];        // [wave][co][v]
-    __shared__ uint16_t aT[4][NC][WG_MAXX + 2];    // [wave][ci][v + 1] (x halo at both ends)
+    __shared__ __align__(16) uint16_t gT[4][NC][WG_PITCH];  // [wave][co][v]
+    __shared__ __align__(16) uint16_t aT[4][NC][WG_PITCH];  // [wave][ci][v + 1] (x halo at both ends)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
@@ -119,47 +301,56 @@ __global__ __launch_bounds__(256) void k_wgrad_partial(const uint16_t* __restric
 #pragma unroll
     for (int t = 0; t < 27; ++t) acc[t] = (f32x4v){0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;  // lane < 16: bias gradient of channel lane
+    uint4 nx[WG_VPL][2];
     for (int row = blockIdx.x * 4 + wv; row < rows; row += gridDim.x * 4) {
         const int y = row % Y;
         const int z = (row / Y) % Z;
         const int b = row / (Y * Z);
         // g row, transposed
-        for (int v = lane; v < X; v += 64) {
-            const uint16_t* src = g + ((((int64_t)b * Z + z) * Y + y) * X + v) * NC;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) gT[wv][c][v] = src[c];
+        wg_load_row(g + (((int64_t)b * Z + z) * Y + y) * X * NC, true, X, 0, X, lane, nx);
+        // LDS regions are per wave and a wave's LDS operations execute in
+        // order; the wavefront-scope fences only keep the compiler from moving
+        // LDS accesses across them (they wait for nothing, so the prefetched
+        // global loads stay in flight)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        wg_store_T(&gT[wv][0][0], WG_PITCH, X, lane, nx);
+        // first neighbour row (dz, dy) = (-1, -1)
+        {
+            const int zz = z - 1, yy = y - 1;
+            const bool ok = zz >= 0 && yy >= 0;
+            wg_load_row(a + (((int64_t)b * Z + (ok ? zz : 0)) * Y + (ok ? yy : 0)) * X * NC, ok, X + 2, 1, X, lane,
+                        nx);
         }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (lane < NC) {
             for (int v = 0; v < X; ++v) bsum += bf2f(gT[wv][lane][v]);
         }
+        // unrolled: the 27 accumulators are then indexed by constants and stay
+        // in registers
+#pragma unroll
         for (int dzy = 0; dzy < 9; ++dzy) {
             const int dz = dzy / 3 - 1, dy = dzy % 3 - 1;
-            const int zz = z + dz, yy = y + dy;
-            const bool ok = zz >= 0 && zz < Z && yy >= 0 && yy < Y;
-            __builtin_amdgcn_wave_barrier();
-            for (int v = lane; v < X + 2; v += 64) {
-                const int xx = v - 1;
-                const bool in = ok && xx >= 0 && xx < X;
-                const uint16_t* src = a + ((((int64_t)b * Z + (in ? zz : 0)) * Y + (in ? yy : 0)) * X + (in ? xx : 0)) * NC;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) aT[wv][c][v] = in ? src[c] : (uint16_t)0;
+            const bool ok = z + dz >= 0 && z + dz < Z && y + dy >= 0 && y + dy < Y;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // after the previous row's LDS reads
+            wg_store_T(&aT[wv][0][0], WG_PITCH, X + 2, lane, nx);
+            if (dzy < 8) {  // next row's loads fly during this row's MFMAs
+                const int zz = z + (dzy + 1) / 3 - 1, yy = y + (dzy + 1) % 3 - 1;
+                const bool nok = zz >= 0 && zz < Z && yy >= 0 && yy < Y;
+                wg_load_row(a + (((int64_t)b * Z + (nok ? zz : 0)) * Y + (nok ? yy : 0)) * X * NC, nok, X + 2, 1, X,
+                            lane, nx);
             }
-            __builtin_amdgcn_s_waitcnt(0);
-            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // before this row's LDS reads
             if (!ok) continue;
 #pragma unroll
             for (int dxi = 0; dxi < 3; ++dxi) {
                 const int t = dzy * 3 + dxi;
                 for (int kc = 0; kc < X / 16; ++kc) {
                     const int v0 = kc * 16 + 4 * kq;
-                    bf16x4 A, Bv;
+                    const bf16x4 A = *reinterpret_cast<const bf16x4*>(&gT[wv][col][v0]);
+                    bf16x4 Bv;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        A[i] = (short)gT[wv][col][v0 + i];
+                    for (int i = 0; i < 4; ++i)
                         Bv[i] = (short)aT[wv][col][v0 + i + dxi];  // a[v + dx] at LDS column v + 1 + dx
-                    }
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, Bv, acc[t], 0, 0, 0);
                 }
             }
@@ -176,17 +367,28 @@ __global__ __launch_bounds__(256) void k_wgrad_partial(const uint16_t* __restric
 }
 
 // dw[t][co][ci] and db[co]: fixed-order sums of the per-wave partials.
-__global__ void k_wgrad_final(const float* __restrict__ partial, int nparts, float* __restrict__ dw,
-                              float* __restrict__ db) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the per-workgroup partials: a workgroup takes 16 outputs and splits
+// the partials into 16 interleaved slices (fixed order in each), then adds
+// the 16 slice sums in order.
+__global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ partial, int nparts,
+                                                     float* __restrict__ dw, float* __restrict__ db) {
+    __shared__ float red[16][17];
     const int per = 27 * NC * NC + NC;
-    if (i >= per) return;
+    const int o = threadIdx.x & 15, sl = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + o;
     float s = 0.f;
-    for (int k = 0; k < nparts; ++k) s += partial[(size_t)k * per + i];
-    if (i < 27 * NC * NC)
-        dw[i] = s;
-    else
-        db[i - 27 * NC * NC] = s;
+    if (i < per)
+        for (int k = sl; k < nparts; k += 16) s += partial[(size_t)k * per + i];
+    red[sl][o] = s;
+    __syncthreads();
+    if (threadIdx.x < 16 && i < per) {
+        float t = 0.f;
+        for (int q = 0; q < 16; ++q) t += red[q][threadIdx.x];
+        if (i < 27 * NC * NC)
+            dw[i] = t;
+        else
+            db[i - 27 * NC * NC] = t;
+    }
 }
 
 // Planar FP32 fields [B][C][vox] -> channels-last bf16 [B][vox][16] (zero beyond C).
@@ -318,17 +520,35 @@ __global__ __launch_bounds__(256) void k_lapmse(const float* __restrict__ out, c
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Per-sample peak |x| over nvox values: one workgroup per sample.
-__global__ __launch_bounds__(256) void k_maxabs(const float* __restrict__ x, int64_t nvox, float* __restrict__ out) {
+// Per-sample peak |x| over nvox values: workgroup (c, b) takes chunk c of
+// sample b and writes its maximum to partial[b * chunks + c]; k_maxabs_final
+// takes the maximum over the chunks (max is exact, so the result does not
+// depend on the split).
+constexpr int MAXABS_CHUNKS = 64;
+__global__ __launch_bounds__(256) void k_maxabs_partial(const float* __restrict__ x, int64_t nvox,
+                                                        float* __restrict__ partial) {
     __shared__ float red[4];
-    const float* p = x + (int64_t)blockIdx.x * nvox;
+    const int b = blockIdx.y;
+    const int64_t per = (nvox + MAXABS_CHUNKS - 1) / MAXABS_CHUNKS;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < nvox ? lo + per : nvox;
+    const float* p = x + (int64_t)b * nvox;
     float m = 0.f;
-    for (int64_t t = threadIdx.x; t < nvox; t += blockDim.x) m = fmaxf(m, fabsf(p[t]));
+    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) m = fmaxf(m, fabsf(p[t]));
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    if (threadIdx.x == 0)
+        partial[(int64_t)b * MAXABS_CHUNKS + blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ void k_maxabs_final(const float* __restrict__ partial, int B, float* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float m = 0.f;
+    for (int c = 0; c < MAXABS_CHUNKS; ++c) m = fmaxf(m, partial[(int64_t)b * MAXABS_CHUNKS + c]);
+    out[b] = m;
 }
 
 // second difference along one axis, 0 at the first and last cell

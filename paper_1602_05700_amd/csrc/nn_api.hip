@@ -8,6 +8,8 @@
 #include "../../include/hgs.h"
 #include "k_nn.hpp"
 
+static_assert(hgs::nn::MAXABS_CHUNKS == HGS_NN_MAXABS_CHUNKS, "scratch size of hgs_nn_maxabs");
+
 using namespace hgs::nn;
 
 namespace {
@@ -48,12 +50,29 @@ hgs_status hgs_nn_conv3d(const uint16_t* in, const uint16_t* w, const float* bia
     if (!dims_ok(B, Z, Y, X)) return nfail(HGS_ERR_ARG, "need B, Z, Y >= 1 and X a positive multiple of 16");
     if (mode < 0 || mode > 3) return nfail(HGS_ERR_ARG, "mode must be 0..3");
     if (mode == HGS_NN_DTANH_BF16 && !aux) return nfail(HGS_ERR_ARG, "DTANH needs aux");
+    if (reinterpret_cast<uintptr_t>(in) % 16 || reinterpret_cast<uintptr_t>(out) % 16 ||
+        reinterpret_cast<uintptr_t>(w) % 16)
+        return nfail(HGS_ERR_ARG, "in, w and out must be 16-byte aligned");
     (void)hipGetLastError();
-    const int64_t waves = (int64_t)B * Z * Y * (X / 16);
-    const int64_t blocks = (waves + 3) / 4;
-    if (blocks > 0x7fffffff) return nfail(HGS_ERR_ARG, "tensor too large");
-    hipLaunchKernelGGL(k_conv3d, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), in, w, bias, B,
-                       Z, Y, X, mode, aux, out);
+    if (X <= CONV_LDS_MAXX) {
+        // input rows staged in LDS, four output rows per workgroup
+        const int64_t blocks = (int64_t)B * Z * ((Y + 3) / 4);
+        if (blocks > 0x7fffffff) return nfail(HGS_ERR_ARG, "tensor too large");
+        const dim3 grid((unsigned)blocks), blk(256);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        switch (X / 16) {
+            case 1: hipLaunchKernelGGL(k_conv3d_lds<1>, grid, blk, 0, st, in, w, bias, B, Z, Y, mode, aux, out); break;
+            case 2: hipLaunchKernelGGL(k_conv3d_lds<2>, grid, blk, 0, st, in, w, bias, B, Z, Y, mode, aux, out); break;
+            case 3: hipLaunchKernelGGL(k_conv3d_lds<3>, grid, blk, 0, st, in, w, bias, B, Z, Y, mode, aux, out); break;
+            default: hipLaunchKernelGGL(k_conv3d_lds<4>, grid, blk, 0, st, in, w, bias, B, Z, Y, mode, aux, out); break;
+        }
+    } else {
+        const int64_t waves = (int64_t)B * Z * Y * (X / 16);
+        const int64_t blocks = (waves + 3) / 4;
+        if (blocks > 0x7fffffff) return nfail(HGS_ERR_ARG, "tensor too large");
+        hipLaunchKernelGGL(k_conv3d, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), in, w,
+                           bias, B, Z, Y, X, mode, aux, out);
+    }
     return nlaunched("hgs_nn_conv3d");
 }
 
@@ -83,7 +102,7 @@ hgs_status hgs_nn_wgrad(const uint16_t* a, const uint16_t* g, int32_t B, int32_t
     const int nb = wgrad_blocks(B, Z, Y);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_wgrad_partial, dim3(nb), dim3(256), 0, st, a, g, B, Z, Y, X, static_cast<float*>(workspace));
-    hipLaunchKernelGGL(k_wgrad_final, dim3((27 * NC * NC + NC + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_wgrad_final, dim3((27 * NC * NC + NC + 15) / 16), dim3(256), 0, st,
                        static_cast<const float*>(workspace), nb * 4, dw, db);
     return nlaunched("hgs_nn_wgrad");
 }
@@ -139,11 +158,13 @@ hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32
     return nlaunched("hgs_nn_lapmse");
 }
 
-hgs_status hgs_nn_maxabs(const float* x, int32_t B, int64_t nvox, float* out, void* stream) {
-    if (!x || !out) return nfail(HGS_ERR_ARG, "x and out must be non-NULL");
-    if (B < 1 || nvox < 1) return nfail(HGS_ERR_ARG, "need B >= 1 and nvox >= 1");
+hgs_status hgs_nn_maxabs(const float* x, int32_t B, int64_t nvox, float* out, float* scratch, void* stream) {
+    if (!x || !out || !scratch) return nfail(HGS_ERR_ARG, "x, out and scratch must be non-NULL");
+    if (B < 1 || B > 65535 || nvox < 1) return nfail(HGS_ERR_ARG, "need 1 <= B <= 65535 and nvox >= 1");
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_maxabs, dim3(B), dim3(256), 0, static_cast<hipStream_t>(stream), x, nvox, out);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_maxabs_partial, dim3(MAXABS_CHUNKS, B), dim3(256), 0, st, x, nvox, scratch);
+    hipLaunchKernelGGL(k_maxabs_final, dim3((B + 255) / 256), dim3(256), 0, st, scratch, B, out);
     return nlaunched("hgs_nn_maxabs");
 }
 

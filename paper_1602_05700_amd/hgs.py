@@ -90,7 +90,7 @@ _SIGS = {
     "hgs_nn_pack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_unpack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_mse": (_i32, [_vp, _vp, _i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]),
-    "hgs_nn_maxabs": (_i32, [_vp, _i32, ctypes.c_int64, _vp, _vp]),
+    "hgs_nn_maxabs": (_i32, [_vp, _i32, ctypes.c_int64, _vp, _vp, _vp]),
     "hgs_nn_features": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _dbl, _vp, _vp]),
     "hgs_nn_compose": (_i32, [_vp, _vp, _vp, _i32, ctypes.c_int64, _dbl, _vp, _vp, _vp]),
     "hgs_nn_lapmse": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp,
@@ -584,11 +584,21 @@ def nn_lapmse(out, target, grad, loss_dev, partials, scratch, ch: int = 0, w: fl
                                  _stream_of(out)))
 
 
-def nn_maxabs(x, out):
-    """x: (B, ...) fp32; out: (B,) fp32 receives the per-sample max |x|."""
+NN_MAXABS_CHUNKS = 64
+
+
+def nn_maxabs(x, out, scratch=None):
+    """x: (B, ...) fp32; out: (B,) fp32 receives the per-sample max |x|;
+    scratch: fp32 with B * NN_MAXABS_CHUNKS elements (allocated if None)."""
+    import torch
+
     B = x.shape[0]
     assert out.numel() == B and x.is_contiguous()
-    _nn_check(_lib.hgs_nn_maxabs(x.data_ptr(), B, x[0].numel(), out.data_ptr(), _stream_of(x)))
+    if scratch is None:
+        scratch = torch.empty(B * NN_MAXABS_CHUNKS, dtype=torch.float32, device=x.device)
+    assert scratch.numel() >= B * NN_MAXABS_CHUNKS
+    _nn_check(_lib.hgs_nn_maxabs(x.data_ptr(), B, x[0].numel(), out.data_ptr(), scratch.data_ptr(),
+                                 _stream_of(x)))
 
 
 def nn_features(rho, phi, scale, c: float, out):

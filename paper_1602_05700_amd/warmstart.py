@@ -160,6 +160,7 @@ class Features:
     def __init__(self, n: int, device, coarse_steps: int = 200, lmax: int = 4):
         self.n, self.device, self.coarse_steps, self.lmax = n, device, coarse_steps, lmax
         self.nh, self.nq = n // 2, n // 4
+        self._batches = {}
 
     def restrict(self, rho):
         """rho: (B, n, n, n) fp32 -> (rho at n/2, rho at n/4)."""
@@ -173,18 +174,25 @@ class Features:
         return r2, r4
 
     def coarse_phi(self, r4):
-        """Damped solves on the n/4 grids (one batch), prolonged to n/2."""
+        """Damped solves on the n/4 grids (one batch), prolonged to n/2.  The
+        batch of grids is kept per batch size and restarted from zero on every
+        call (its ghosts are rebuilt by the first substep group)."""
         import torch
 
         B, m = r4.shape[0], self.nq
         dx = 2.0 / m
-        b = hgs.Batch([m] * B, storage="f32", lmax=self.lmax, eta=eta_critical(m, dx), device=self.device)
+        if B not in self._batches:
+            self._batches[B] = (hgs.Batch([m] * B, storage="f32", lmax=self.lmax, eta=eta_critical(m, dx),
+                                          device=self.device),
+                                torch.zeros((m, m, m), dtype=torch.float32, device=r4.device))
+        b, zero = self._batches[B]
+        for g in b.grids:
+            g.set_state(zero, None, 0.4 * dx)
         rhos = [r4[i].contiguous() for i in range(B)]
         b.step(rhos, 1.0, 0.4 * dx, self.coarse_steps)
         phi4 = torch.stack([g.potential(with_phidot=False)[0] for g in b.grids])
         phi2 = torch.empty((B, self.nh, self.nh, self.nh), dtype=torch.float32, device=r4.device)
         hgs.nn_prolong2(phi4, phi2)
-        b.close()
         return phi2
 
     @property

@@ -34,7 +34,7 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
 
 
-SHAPES = [(1, 3, 4, 16), (2, 6, 5, 32), (1, 8, 8, 64)]
+SHAPES = [(1, 3, 4, 16), (2, 6, 5, 32), (1, 8, 8, 64), (1, 2, 7, 96), (1, 3, 5, 128)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
