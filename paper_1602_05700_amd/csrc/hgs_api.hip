@@ -279,8 +279,41 @@ bool use_vec(const Layout& L) {
     return L.nx % Vec16<S>::N == 0;
 }
 
+// Boundaries whose ghosts follow the interior every substep (one substep per
+// stencil launch, then a ghost launch), as opposed to ghosts frozen over a
+// hydrodynamical step (multipole, user).
+bool local_bc(int bc) { return bc == HGS_BC_ROBIN || bc == HGS_BC_OUTGOING || bc == HGS_BC_PERIODIC; }
+
+// Buffers that hold phi^n at some point of the coming nsub substeps, the
+// last state included: a fused launch reads (cur, old) and makes the other
+// two buffers (phi^{n+T}, phi^{n+T-1}); a streaming substep writes the new
+// level over old, which becomes cur.  Only these read their ghosts (the
+// update reads phi^{n-1} at the cell alone), so only they need this
+// hydrodynamical step's ghosts.  Bit k of the result = buffer k.
+int ghost_buffers(const hgs_ctx* c, int nsub) {
+    const int T = local_bc(c->cfg.bc) ? 1 : c->tblock;
+    int cur = c->cur, old = c->old;
+    int mask = 1 << cur;
+    while (nsub > 0) {
+        if (T > 1 && nsub >= T) {
+            int o0 = -1, o1 = -1;
+            for (int k = 0; k < 4; ++k)
+                if (k != cur && k != old) (o0 < 0 ? o0 : o1) = k;
+            cur = o0;
+            old = o1;
+            nsub -= T;
+        } else {
+            std::swap(cur, old);
+            nsub -= 1;
+        }
+        mask |= 1 << cur;
+    }
+    return mask;
+}
+
+// mask: the buffers that receive the ghosts (bit k = buffer k)
 template <typename S>
-void run_moments_and_ghosts(hgs_ctx* c, const void* rho) {
+void run_moments_and_ghosts(hgs_ctx* c, const void* rho, int mask) {
     const MomGeom g = geom(c);
     Timed tm(c, HGS_KERNEL_MULTIPOLE);
     dim3 blk(64, 4);
@@ -294,15 +327,14 @@ void run_moments_and_ghosts(hgs_ctx* c, const void* rho) {
                        c->cfg.dx * c->cfg.dx * c->cfg.dx, c->mom);
     const int64_t nf = 2 * ((int64_t)c->L.nz * c->L.ny + (int64_t)c->L.nz * c->L.nx + (int64_t)c->L.ny * c->L.nx);
     const int maxfast = std::max(c->L.nx, c->L.ny), maxslow = std::max(c->L.ny, c->L.nz);
+    S* b[4];
+    int nb = 0;
+    for (int k = 0; k < 4; ++k) b[k] = (mask >> k & 1) ? B<S>(c, k) : nullptr, nb += (mask >> k) & 1;
     hipLaunchKernelGGL(k_ghosts<S>, dim3((maxfast + 255) / 256, maxslow, 6), dim3(256), 0, c->stream, c->L, g,
-                       c->cfg.lmax, c->cfg.G, c->mom, B<S>(c, 0), B<S>(c, 1), B<S>(c, 2), B<S>(c, 3));
-    tm.end((double)sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz + 4.0 * sizeof(S) * (double)nf, 0.0);
+                       c->cfg.lmax, c->cfg.G, c->mom, b[0], b[1], b[2], b[3]);
+    tm.end((double)sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz + (double)nb * sizeof(S) * (double)nf, 0.0);
 }
 
-// Boundaries whose ghosts follow the interior every substep (one substep per
-// stencil launch, then a ghost launch), as opposed to ghosts frozen over a
-// hydrodynamical step (multipole, user).
-bool local_bc(int bc) { return bc == HGS_BC_ROBIN || bc == HGS_BC_OUTGOING || bc == HGS_BC_PERIODIC; }
 
 LocalGeom local_geom(const hgs_ctx* c) {
     return LocalGeom{c->cfg.x0, c->cfg.y0, c->cfg.z0, c->cfg.dx, c->cfg.origin[0], c->cfg.origin[1], c->cfg.origin[2]};
@@ -707,7 +739,7 @@ hgs_status hgs_step(hgs_ctx* ctx, const void* rho, double c_g, double dt, int32_
     if (vs != HGS_OK) return vs;
     (void)hipGetLastError();
     if (ctx->cfg.bc == HGS_BC_MULTIPOLE) {
-        DISPATCH(ctx, run_moments_and_ghosts, ctx, rho);
+        DISPATCH(ctx, run_moments_and_ghosts, ctx, rho, ghost_buffers(ctx, nsub));
         ctx->have_moments = true;
     }
     if (ctx->cfg.bc == HGS_BC_PERIODIC) DISPATCH(ctx, run_mean, ctx, rho);
@@ -1332,7 +1364,7 @@ hgs_status hgs_step_batch(hgs_batch* b, const void* const* rho, const double* c_
     for (int i = 0; i < b->n; ++i) {
         hgs_ctx* c = b->grids[i];
         if (c->cfg.bc == HGS_BC_MULTIPOLE) {
-            DISPATCH(c, run_moments_and_ghosts, c, rho[i]);
+            DISPATCH(c, run_moments_and_ghosts, c, rho[i], 0xF);
             c->have_moments = true;
         }
         if (c->dt_prev > 0.0 && dt[i] != c->dt_prev) DISPATCH(c, run_rescale, c, dt[i] / c->dt_prev);
