@@ -287,7 +287,11 @@ hgs_status hgs_destroy_batch(hgs_batch* b);
  * in uint16 unless stated; weights are (27 taps, 16 out, 16 in) bfloat16 with
  * tap t = (dz+1)*9 + (dy+1)*3 + (dx+1); the convolution is a correlation with
  * zero padding ("same" size): out[v][co] = sum_t,ci w[t][co][ci] in[v+tap][ci].
- * All pointers are device pointers; all calls are asynchronous on `stream`. */
+ * All pointers are device pointers owned by the caller; all calls are
+ * asynchronous on `stream` (NULL = null stream) and validate on the host
+ * before launching: a NULL required pointer, a size out of range or a
+ * misaligned tensor returns HGS_ERR_ARG and launches nothing, a failed launch
+ * HGS_ERR_DEVICE; the reason is in hgs_nn_last_error(). */
 #define HGS_NN_CHANNELS 16
 typedef enum {
     HGS_NN_F32 = 0,        /* out (FP32) = conv + bias */
@@ -295,7 +299,8 @@ typedef enum {
     HGS_NN_DTANH_BF16 = 2, /* out (bf16) = conv * (1 - aux^2), aux a tanh output (backward) */
     HGS_NN_BF16 = 3        /* out (bf16) = conv + bias */
 } hgs_nn_mode;
-/* X must be a multiple of 16; bias may be NULL (zero); aux only for DTANH. */
+/* X must be a multiple of 16; in, w and out 16-byte aligned; bias may be NULL
+ * (zero); aux only for DTANH. */
 hgs_status hgs_nn_conv3d(const uint16_t* in, const uint16_t* w, const float* bias, int32_t B, int32_t Z, int32_t Y,
                          int32_t X, int32_t mode, const uint16_t* aux, void* out, void* stream);
 /* wt[26 - t][ci][co] = w[t][co][ci]: the weights of the input-gradient convolution. */
