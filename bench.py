@@ -119,6 +119,76 @@ def run_batched(dev, nsub=500, seed=2, count=64):
             "graph": b.used_graph, "tblock": b.grids[0].tblock}
 
 
+def run_configs(dev):
+    """Throughput of the two smaller configurations, besides the headline one:
+    the 64^3 uniform sphere (FP64, lmax 0, zero start, 2000 substeps, eta = 0
+    as in Eq. 2 and critically damped) and the 256^3 rotating 8-blob mixture
+    (seed 0, speed 0.1 c_g at radius 1, lmax 4, 4 substeps per hydro step,
+    250 hydro steps, FP64 and FP32 storage, moments + ghosts + substeps +
+    gradient timed; 64 rotated densities generated beforehand and cycled)."""
+    import math
+
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import hgs
+
+    out = {}
+    n = 64
+    dx = 2.0 / n
+    dt = 0.4 * dx
+    rho = torch.from_numpy(workloads.sphere_density(n, 0.25)).to(dev)
+    lam = 3 * (4 / dx ** 2) * math.sin(math.pi / (2 * (n + 1))) ** 2  # slowest Dirichlet mode
+    for label, eta in (("eta_0", 0.0), ("eta_critical", 2.0 * math.sqrt(lam))):
+        s = hgs.Solver(n, storage="f64", lmax=0, eta=eta, device=dev)
+        s.step(rho, 1.0, dt, 8)  # warm-up
+        s2 = hgs.Solver(n, storage="f64", lmax=0, eta=eta, device=dev)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s2.stream)
+        s2.step(rho, 1.0, dt, 2000)
+        e1.record(s2.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out.setdefault("sphere_64_f64", {})[label] = {
+            "substeps": 2000, "ms": round(ms, 3), "Gcell_updates_per_s": round(n ** 3 * 2000 / (ms / 1e3) / 1e9, 2),
+            "R_f": float(s2.residual(rho)[1])}
+        s.close()
+        s2.close()
+    n, nsub, steps = 256, 4, 250
+    dx = 2.0 / n
+    dt = 0.4 * dx
+    blobs = workloads.blob_params(0, 8)
+    for storage, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        rhos = [workloads.blob_density_torch(n, blobs.rotated(0.1 * nsub * dt * h), dev, tdt) for h in range(64)]
+        s = hgs.Solver(n, storage=storage, lmax=4, eta=0.0, device=dev)
+        g = [torch.empty((n, n, n), dtype=tdt, device=dev) for _ in range(3)]
+        for h in range(3):
+            s.step(rhos[h], 1.0, dt, nsub)
+            s.accel(g)
+        torch.cuda.synchronize()
+        s.timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        for h in range(steps):
+            s.step(rhos[h % 64], 1.0, dt, nsub)
+            s.accel(g)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kinds = {k: s.timing_read(k) for k in ("stencil", "multipole", "gradient")}
+        s.timing(False)
+        out.setdefault("rotating_256", {})[storage] = {
+            "hydro_steps": steps, "tblock": s.tblock, "ms_per_hydro_step": round(ms / steps, 4),
+            "Gcell_updates_per_s": round(n ** 3 * nsub * steps / (ms / 1e3) / 1e9, 2),
+            "us_per_launch": {k: round(d["ms"] / max(d["launches"], 1) * 1e3, 1) for k, d in kinds.items()},
+            "stencil_GBps_algorithmic": round(kinds["stencil"]["bytes"] / kinds["stencil"]["ms"] / 1e6, 0)}
+        s.close()
+        del rhos, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_warmstart(dev, count=8, n=128, tol=1e-4):
     """Substeps of the critically damped FP32 solver to R_b < tol on 128^3
     blob mixtures (held-out seeds 20000..), from the zero start and from the
@@ -209,6 +279,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched measurement")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the steps-to-1e-4 warm-start measurement")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 64^3 sphere and 256^3 rotating-blob runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (for scaling HBM counters)")
     args = ap.parse_args()
@@ -332,6 +403,10 @@ def main():
         log("[bench] batched: 64 uneven grids, 500 substeps")
         line["batched"] = run_batched(dev)
         log(f"[bench]   {line['batched']}")
+    if not args.no_configs:
+        log("[bench] smaller configurations: 64^3 sphere (FP64), 256^3 rotating blobs (FP64, FP32)")
+        line["configs"] = run_configs(dev)
+        log(f"[bench]   {line['configs']}")
     if not args.no_warmstart:
         log("[bench] warm start: steps to R_b < 1e-4 at 128^3, zero vs learned")
         line["warm_start"] = run_warmstart(dev)
