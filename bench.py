@@ -373,7 +373,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-storage/f64-math",
+        "dtype": "f32 (storage and substeps; f64 moments, boundary and gradient)",
         "data": "synthetic",
         "config": {
             "workload": f"hyperbolic gravity, {n}^3 grid, 16 rotating Gaussian blobs, FP32 storage, lmax 4, "
