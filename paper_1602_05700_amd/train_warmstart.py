@@ -101,9 +101,12 @@ def train(net, P, tgt, args, lap_w, dev, log_prefix=""):
             "lap_w": lap_w}
 
 
-def evaluate(net, data, seeds, n, feats, args, dev, controls=True, tag="eval"):
+def evaluate(net, data, seeds, n, feats, args, dev, controls=True, tag="eval", criteria=()):
     """Substeps to R_b < tol from the zero start, the coarse cue alone, the
-    learned start (zero start as fallback) and the restricted exact solution."""
+    learned start (zero start as fallback) and the restricted exact solution.
+    criteria: further criteria ("R_f" in FP64 storage, whose FP32 floor at
+    128^3 lies above 1e-4; "E" against the converged target) whose substep
+    counts from the zero and the learned start are recorded as well."""
     import torch
 
     from paper_1602_05700_amd import hgs, warmstart as ws
@@ -134,6 +137,13 @@ def evaluate(net, data, seeds, n, feats, args, dev, controls=True, tag="eval"):
             row.update({"coarse": coarse[0], "ideal": ideal[0]})
             row["R0"].update({"coarse": coarse[1], "ideal": ideal[1]})
             row["E0"].update({"coarse": e(pc[0]), "ideal": e(pi[0])})
+        for crit in criteria:
+            kw = {"storage": "f64"} if crit == "R_f" else {}
+            kw.update({"metric": crit, "ref": exact if crit == "E" else None})
+            z_c = ws.steps_to_tolerance(rho, n, args.tol, **kw)
+            l_c = ws.steps_to_tolerance(rho, n, args.tol, start=(phi[0], pd[0]), **kw)
+            row[f"zero_{crit}"], row[f"learned_{crit}"] = z_c[0], l_c[0]
+            row["R0"].update({f"zero_{crit}": z_c[1], f"learned_{crit}": l_c[1]})
         rows.append(row)
         log(f"[{tag}] seed {seed}: zero {zero[0]} learned {learned[0]}{' (fallback)' if fallback else ''}"
             + (f" coarse {row['coarse']} ideal {row['ideal']}" if controls else "")
@@ -157,6 +167,11 @@ def summarise(rows, cc):
         out.update({"steps_coarse": stats("coarse", cc), "steps_ideal": stats("ideal"),
                     "ratio_coarse": z["median"] / stats("coarse", cc)["median"],
                     "ratio_ideal": z["median"] / stats("ideal")["median"]})
+    for crit in ("R_f", "E"):
+        if f"zero_{crit}" in rows[0]:
+            zc, lc = stats(f"zero_{crit}"), stats(f"learned_{crit}", cc)
+            out[f"criterion_{crit}"] = {"steps_zero": zc, "steps_learned": lc,
+                                        "ratio": zc["median"] / lc["median"]}
     return out
 
 
@@ -178,6 +193,8 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1602_05700_amd", "warmstart_weights.npz"))
     ap.add_argument("--report", default=os.path.join(ROOT, "gpurun_out", "warmstart_report.json"))
     ap.add_argument("--eval-only", action="store_true")
+    ap.add_argument("--criteria", default="R_f,E",
+                    help="criteria besides R_b counted on the held-out densities (comma-separated, or empty)")
     args = ap.parse_args()
 
     import torch
@@ -226,7 +243,8 @@ def main():
     # ---- held-out evaluation
     test_seeds = list(range(20000, 20000 + args.test))
     data = build(test_seeds, n, feats, dev, args.chunk, args.target_steps)
-    rows = evaluate(net, data, test_seeds, n, feats, args, dev, controls=True)
+    crits = tuple(c for c in args.criteria.split(",") if c)
+    rows = evaluate(net, data, test_seeds, n, feats, args, dev, controls=True, criteria=crits)
     ev = summarise(rows, cc)
     ev["target_max_Rb"] = float(max(data[5]))
     ev["rows"] = rows
@@ -238,6 +256,10 @@ def main():
         f"learned {ev['steps_learned']['median']:.1f} ideal {ev['steps_ideal']['median']}; "
         f"gain learned {ev['ratio_learned']:.2f}x coarse {ev['ratio_coarse']:.2f}x ideal {ev['ratio_ideal']:.2f}x; "
         f"fallback {ev['fallback_rate']:.2f}")
+    for crit in crits:
+        c = ev[f"criterion_{crit}"]
+        log(f"[eval] {crit} < {args.tol:g}: median steps zero {c['steps_zero']['median']} "
+            f"learned {c['steps_learned']['median']:.1f}, gain {c['ratio']:.2f}x")
 
 
 if __name__ == "__main__":

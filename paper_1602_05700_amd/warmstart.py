@@ -259,10 +259,19 @@ def converged_phi(rhos, n: int, device, steps: int = 1500, storage: str = "f64",
 
 
 def steps_to_tolerance(rho, n: int, tol: float, start=None, max_steps: int = 4000, check: int = 4,
-                       storage: str = "f32", lmax: int = 4, device="cuda"):
-    """Substeps of the damped fine solver until R_b < tol, from zero or from
-    start = (phi, phidot).  Returns (steps, R_b at start, R_b at end)."""
+                       storage: str = "f32", lmax: int = 4, device="cuda", metric: str = "R_b", ref=None):
+    """Substeps of the damped fine solver until the criterion falls below tol,
+    from zero or from start = (phi, phidot).  metric: "R_b" (the residual
+    relative to the linear system's right-hand side, boundary terms
+    included), "R_f" (relative to the source alone) or "E" (relative
+    distance to the converged potential ref).  Returns (steps, criterion
+    after the first check, criterion at the end)."""
     import torch
+
+    if metric not in ("R_b", "R_f", "E"):
+        raise ValueError(f"unknown criterion {metric!r}")
+    if metric == "E" and ref is None:
+        raise ValueError("E needs the converged potential ref")
 
     dx = 2.0 / n
     dt = 0.4 * dx
@@ -273,12 +282,18 @@ def steps_to_tolerance(rho, n: int, tol: float, start=None, max_steps: int = 400
     # `check` substeps from the chosen start and count those substeps
     if start is not None:
         s.set_state(start[0].to(dtype).contiguous(), start[1].to(dtype).contiguous(), dt)
+    if metric == "E":
+        ref64 = ref.to(torch.float64)
+        ref_norm = float(ref64.norm())
     r0 = None
     steps = 0
     while steps < max_steps:
         s.step(r, 1.0, dt, check)
         steps += check
-        rb = s.residual(r)[0]
+        if metric == "E":
+            rb = float((s.potential(with_phidot=False)[0].to(torch.float64) - ref64).norm()) / ref_norm
+        else:
+            rb = s.residual(r)[0 if metric == "R_b" else 1]
         if r0 is None:
             r0 = rb
         if rb < tol:
