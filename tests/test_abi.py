@@ -165,3 +165,13 @@ def test_embed_extract_host_checks():
     assert L.hgs_embed(a, 4, 4, 4, 1, a, 9, None) == hgs.HGS_ERR_ARG
     assert L.hgs_extract(a, 8000, 4, 4, 200, a, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
     assert L.hgs_extract(a, 4, 4, 4, 1, None, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
+
+
+def test_warmstart_criterion_checks():
+    """Convergence criteria are checked before any solver is built."""
+    from paper_1602_05700_amd import warmstart as ws
+
+    with pytest.raises(ValueError):
+        ws.steps_to_tolerance(None, 16, 1e-4, metric="R_x")
+    with pytest.raises(ValueError):
+        ws.steps_to_tolerance(None, 16, 1e-4, metric="E")  # E needs the converged reference
