@@ -191,7 +191,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=32)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1602_05700_amd", "warmstart_weights.npz"))
-    ap.add_argument("--report", default=os.path.join(ROOT, "gpurun_out", "warmstart_report.json"))
+    ap.add_argument("--report", default="warmstart_report.json")
     ap.add_argument("--eval-only", action="store_true")
     ap.add_argument("--criteria", default="R_f,E",
                     help="criteria besides R_b counted on the held-out densities (comma-separated, or empty)")
