@@ -64,8 +64,11 @@ def counter_traffic(kernel: str, launches_cells: int):
         return None
 
 
-def cpu_baseline(rho_host, n, nsub, dt):
-    """The FP64 oracle, as it stands, over one hydro step of the same workload."""
+def cpu_baseline(rho_host, n, nsub, dt, phi0_host=None, gpu=None):
+    """The FP64 oracle, as it stands, over one hydro step of the same workload
+    (from phi0 when given, else from zero).  gpu = (phi, gx, gy, gz) of the
+    same hydro step from the same state, as host arrays: their error against
+    the oracle, max |a - b| / max |b| per field, is reported as well."""
     import numpy as np
 
     from oracle import core
@@ -74,17 +77,26 @@ def cpu_baseline(rho_host, n, nsub, dt):
     g = Grid.cube(n)
     o = Oracle(g, lmax=4, eta=0.0)
     r = np.ascontiguousarray(rho_host, dtype=np.float64)
+    if phi0_host is not None:
+        o.set_state(np.asarray(phi0_host, dtype=np.float64), None, dt)
     t0 = time.perf_counter()
     o.step(r, 1.0, dt, nsub)
-    o.accel()
+    acc = o.accel()
     t = time.perf_counter() - t0
-    return {
+    out = {
         "value": nsub * n ** 3 / t / 1e9,
         "unit": "Gcell-updates/s",
         "cores": core.max_threads(),
         "kind": "oracle",
         "sample": f"one hydro step ({n}^3, moments+ghosts, {nsub} substeps, gradient) in {t:.2f} s",
     }
+    if gpu is not None:
+        rel = lambda a, b: float(np.max(np.abs(np.asarray(a, dtype=np.float64) - b)) / np.max(np.abs(b)))
+        out["gpu_vs_oracle"] = {"phi": rel(gpu[0], o.potential()[0]),
+                                "accel": max(rel(a, b) for a, b in zip(gpu[1:], acc)),
+                                "metric": "max|gpu - oracle| / max|oracle| per field, FP32 storage",
+                                "tolerance": 1e-4}
+    return out
 
 
 def run_batched(dev, nsub=500, seed=2, count=64):
@@ -271,7 +283,7 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=25)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--nsub", type=int, default=4)
@@ -412,9 +424,19 @@ def main():
         line["warm_start"] = run_warmstart(dev)
         log(f"[bench]   {line['warm_start']}")
     if not args.no_cpu_baseline:
-        log("[bench] CPU baseline (oracle, one hydro step)")
+        log("[bench] CPU baseline (oracle, one hydro step) and the GPU's error against it")
         rho0 = workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * W), dev, torch.float32)
-        line["cpu_baseline"] = cpu_baseline(rho0.cpu().numpy(), n, nsub, dt)
+        # the same hydro step on the GPU from the same smooth non-zero start
+        ax = -1.0 + (torch.arange(n, device=dev, dtype=torch.float64) + 0.5) * dx
+        phi0 = (-1.0 / torch.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+                                  + 0.09)).to(torch.float32)
+        v = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=s.tblock, device=dev)
+        v.set_state(phi0, None, dt)
+        v.step(rho0, c_g, dt, nsub)
+        gpu = [v.potential(with_phidot=False)[0].cpu().numpy()] + [a.cpu().numpy() for a in v.accel()]
+        v.close()
+        line["cpu_baseline"] = cpu_baseline(rho0.cpu().numpy(), n, nsub, dt, phi0.cpu().numpy(), gpu)
+        log(f"[bench]   {line['cpu_baseline']}")
     print(json.dumps(line), flush=True)
 
 
