@@ -198,7 +198,67 @@ def run_configs(dev):
         s.close()
         del rhos, g
         torch.cuda.empty_cache()
+    out["next_rows_256_f32"] = run_next_rows(dev)
     return out
+
+
+def run_next_rows(dev, n=256, nsub=4, steps=20):
+    """Throughput of the parts built beyond the multipole path, at 256^3 FP32
+    on the same 8-blob density (eta = 0, dt = 0.4 dx): the local boundaries
+    (one substep per launch plus a ghost launch), the extended grid (32 vacuum
+    cells on every side, outgoing boundary, rho embedded and g extracted every
+    hydro step) and the hydro-coupled driver (signal-speed reduction over
+    c_s and v, k_g = 5, Courant numbers 0.3: 5 substeps per hydro step).  Each
+    entry: ms per hydro step (step + gradient) and cell updates per second."""
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import hgs
+
+    dx = 2.0 / n
+    dt = 0.4 * dx
+    rho = workloads.blob_density_torch(n, workloads.blob_params(0, 8), dev, torch.float32)
+    res = {}
+
+    def timed(label, run, updates):
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[label] = {"ms_per_hydro_step": round(ms, 4), "Gcell_updates_per_s": round(updates / (ms / 1e3) / 1e9, 2)}
+
+    g = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in range(3)]
+    for bc in ("robin", "outgoing", "periodic"):
+        sv = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, bc=bc, device=dev)
+        timed(bc, lambda: (sv.step(rho, 1.0, dt, nsub), sv.accel(g)), n ** 3 * nsub)
+        sv.close()
+    e = 32
+    ex = hgs.ExtendedSolver(n, e, bc="outgoing", storage="f32", lmax=4, eta=0.0, device=dev)
+    timed("extended_outgoing_ext32", lambda: (ex.step(rho, 1.0, dt, nsub), ex.accel()), (n + 2 * e) ** 3 * nsub)
+    res["extended_outgoing_ext32"]["grid"] = n + 2 * e
+    ex.close()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    cs = 0.05 + 0.05 * torch.rand((n, n, n), device=dev, generator=gen)
+    v = [0.05 * torch.randn((n, n, n), device=dev, generator=gen) for _ in range(3)]
+    sv = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, device=dev)
+    info = {}
+
+    def driver():
+        info["step"] = sv.hydro_step(rho, cs, v, k_g=5.0, courant_hydro=0.3, courant_grav=0.3)
+        sv.accel(g)
+
+    driver()
+    timed("driver_kg5", driver, n ** 3 * info["step"][1])
+    res["driver_kg5"]["nsub"] = info["step"][1]
+    sv.close()
+    return res
 
 
 def run_warmstart(dev, count=8, n=128, tol=1e-4):
