@@ -131,6 +131,7 @@ __global__ __launch_bounds__(256) void k_conv3d_lds(const uint16_t* __restrict__
     const int yb = blockIdx.x % ybl;
     const int z = (blockIdx.x / ybl) % Z;
     const int b = blockIdx.x / (ybl * Z);
+    if (b >= B) return;  // whole workgroup, before the barrier (the grid is B Z ceil(Y/4))
     const int y0 = yb * 4;
     // stage: 2 halves of 8 channels (16 bytes) per voxel, then the weights.
     // Every load of a thread is issued before its first LDS store, so the
