@@ -554,3 +554,80 @@ def test_fp32_storage_keeps_fp64_accuracy_at_convergence(gpu_lib):
     e_inf = rel(out["f32"], out["f64"])
     e_l2 = float(np.linalg.norm(out["f32"] - out["f64"]) / np.linalg.norm(out["f64"]))
     assert e_inf < 2e-6 and e_l2 < 1e-6, (e_inf, e_l2)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_grid_1024_f32_large_offsets(gpu_lib):
+    """1024^3 FP32 (4.6 GB per state buffer, byte offsets past 2^32): the ghost
+    shell against the oracle's moments and boundary over every face cell, one
+    streaming substep and the gradient at sampled cells (the extreme indices
+    included) against the update and the central difference evaluated on the
+    host from the GPU's own inputs, and a fused 4-substep launch bitwise equal
+    to four streaming substeps."""
+    import torch
+
+    n = 1024
+    g = Grid.cube(n)
+    dt = 0.4 * g.dx
+    rho = workloads.blob_density_torch(n, workloads.blob_params(1, 16), "cuda", torch.float32)
+    ax = -1.0 + (torch.arange(n, device="cuda", dtype=torch.float64) + 0.5) * g.dx
+    phi0 = (-1.0 / torch.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+                              + 0.09)).to(torch.float32)
+    del ax
+    a = gpu_lib.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=1)
+    a.set_state(phi0, None, dt)
+    a.step(rho, 1.0, dt, 1)
+    # ghosts: the oracle's moments of the same (FP32) density and its boundary
+    faces = gpu_lib.flat_to_faces(host(a.get_boundary()), (n, n, n))
+    r64 = host(rho)
+    q = core.moments(g, r64, 4)
+    P = core.padded(g)
+    core.boundary(g, q, 4, 1.0, P)
+    for got, want in zip(faces, core.faces(P)):
+        assert rel(got, want) < 1e-6
+    del P, r64
+    # one substep at sampled cells: phi + kk sum(nb - phi) - (c dt)^2 4 pi G rho (eta = 0, phidot = 0)
+    rng = np.random.default_rng(7)
+    ext = np.array([0, 1, 511, 512, 1022, 1023])
+    idx = np.concatenate([np.stack(np.meshgrid(ext, ext, ext, indexing="ij"), -1).reshape(-1, 3),
+                          rng.integers(0, n, (400, 3))])
+    p0 = phi0.double()
+    phi1 = a.potential(with_phidot=False)[0]
+
+    def val(arr, k, j, i):  # interior value or ghost (faces x-, x+, y-, y+, z-, z+)
+        if i < 0 or i >= n:
+            return float(faces[0 if i < 0 else 1][k, j])
+        if j < 0 or j >= n:
+            return float(faces[2 if j < 0 else 3][k, i])
+        if k < 0 or k >= n:
+            return float(faces[4 if k < 0 else 5][j, i])
+        return float(arr[k, j, i])
+
+    kk = (dt / g.dx) ** 2
+    cs = dt * dt * 4.0 * np.pi
+    worst = 0.0
+    for k, j, i in idx:
+        c = float(p0[k, j, i])
+        s6 = sum(val(p0, k + dk, j + dj, i + di) - c
+                 for dk, dj, di in ((0, 0, -1), (0, 0, 1), (0, -1, 0), (0, 1, 0), (-1, 0, 0), (1, 0, 0)))
+        want = c + kk * s6 - cs * float(rho[k, j, i])
+        worst = max(worst, abs(float(phi1[k, j, i]) - want) / abs(want))
+    assert worst < 1e-6, worst
+    # gradient of phi1, bitwise: -(phi[+1] - phi[-1]) / (2 dx) in FP64, rounded to FP32
+    gx, gy, gz = a.accel()
+    hid = 0.5 / g.dx
+    for k, j, i in idx[:120]:
+        for comp, (dk, dj, di) in zip((gx, gy, gz), ((0, 0, 1), (0, 1, 0), (1, 0, 0))):
+            want = np.float32(-(val(phi1, k + dk, j + dj, i + di) - val(phi1, k - dk, j - dj, i - di)) * hid)
+            assert np.float32(comp[k, j, i].item()) == want, (k, j, i)
+    del gx, gy, gz, phi1
+    # fused launch of 4 substeps = 4 streaming substeps, bitwise, over the whole grid
+    a.step(rho, 1.0, dt, 3)
+    b = gpu_lib.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=4)
+    b.set_state(phi0, None, dt)
+    b.step(rho, 1.0, dt, 4)
+    pa, pb = a.potential(with_phidot=False)[0], b.potential(with_phidot=False)[0]
+    assert torch.equal(pa, pb)
+    a.close()
+    b.close()
