@@ -41,6 +41,9 @@ arXiv:1602.05700), and what pins it (tests/test_oracle_pins.py):
   convergence on the Gaussian.
 * ``poisson.py`` -- discrete Dirichlet Poisson solve by DST-I, the limit the
   method converges to (Eq. (1)); pinned by a dense LU solve on small grids.
+  ``mean_relative_error`` is the paper's average relative error against the
+  Poisson solution (Sec. 4, Eqs. (5)-(6)), pinned by closed forms (uniform and
+  alternating relative offsets).
 * ``analytic.py`` -- closed forms (uniform sphere, Gaussian, cube self
   potential) and brute-force sums used as pins.
 * ``nn.py`` -- FP64 3D convolution network pieces (forward and backward) for the

@@ -82,3 +82,15 @@ def with_solution(g: Grid, P: np.ndarray, phi: np.ndarray) -> np.ndarray:
     Q = P.copy()
     interior(Q)[...] = phi
     return Q
+
+
+def mean_relative_error(phi_h: np.ndarray, phi_p: np.ndarray) -> float:
+    """The paper's average relative error (Sec. 4, Eq. 6): the root mean square,
+    over the volume, of the pointwise relative difference (Eq. 5)
+    (phi_h - phi_p) / phi_p between the wave-equation potential and the
+    Poisson solution of the same density.  On a uniform grid the volume
+    integrals are sums over cells with equal weights."""
+    h = np.asarray(phi_h, dtype=np.float64)
+    p = np.asarray(phi_p, dtype=np.float64)
+    d = (h - p) / p
+    return float(np.sqrt(np.mean(d * d)))

@@ -10,7 +10,7 @@ import pytest
 import workloads
 from oracle import core, poisson
 from oracle.core import Oracle, interior, padded
-from test_gpu_parity import F64_TOL, dens, grid_of, host, rel, solver, to_dev
+from test_gpu_parity import F64_TOL, dens, grid_of, host, npdt, rel, solver, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -141,3 +141,53 @@ def test_error_estimate_eq12(gpu_lib):
     assert (errs[2.0] - floor) / (errs[4.0] - floor) > 2.8, errs
     for k in ks:
         assert errs[k] < 1.0 / k ** 2, errs
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_tracking_256_rotating_eq6():
+    """The 256^3 rotating configuration (8 blobs, seed 0, speed 0.1 c_g at
+    radius 1, centres turned before each hydro step, lmax 4, 4 substeps per
+    hydro step, eta = 0) started from the Poisson solution with the time
+    derivative of rigid rotation: the paper's average relative error (Eq. 6)
+    against the Poisson solution of the current density stays below 1e-2
+    (it scales as (v / c_g)^2, Eq. 12) in FP64 and FP32 storage, and the two
+    storages agree far below that."""
+    import torch
+
+    from paper_1602_05700_amd import hgs
+
+    n, nsub, omega = 256, 4, 0.1
+    g = grid_of((n, n, n))
+    dt = 0.4 * g.dx
+    base = workloads.blob_params(0, 8)
+    x, y, z = workloads.centred_axes((n, n, n), g.dx)
+    rho_h = lambda h: workloads.blob_density_axes(x, y, z, base.rotated(omega * nsub * dt * h), dtype=np.float64)
+    r0 = rho_h(0)
+    phi0 = _poisson(g, r0)
+    Pf = padded(g)
+    interior(Pf)[...] = phi0
+    core.boundary(g, core.moments(g, r0, 4), 4, 1.0, Pf)
+    dpx = (Pf[1:-1, 1:-1, 2:] - Pf[1:-1, 1:-1, :-2]) / (2 * g.dx)
+    dpy = (Pf[1:-1, 2:, 1:-1] - Pf[1:-1, :-2, 1:-1]) / (2 * g.dx)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    pd0 = -omega * (X * dpy - Y * dpx)
+    del Pf, dpx, dpy, Z, Y, X
+    checks = (10, 30, 60)
+    refs = {h: _poisson(g, rho_h(h - 1)) for h in checks}  # the density of the last step taken
+    errs = {}
+    finals = {}
+    for storage, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        s = solver(hgs, (n, n, n), storage=storage, lmax=4, eta=0.0)
+        s.set_state(to_dev(phi0.astype(npdt(storage))), to_dev(pd0.astype(npdt(storage))), dt)
+        for h in range(1, checks[-1] + 1):
+            rho_dev = workloads.blob_density_torch(n, base.rotated(omega * nsub * dt * (h - 1)), "cuda", tdt)
+            s.step(rho_dev, 1.0, dt, nsub)
+            if h in refs:
+                errs[(storage, h)] = poisson.mean_relative_error(host(s.potential()[0]), refs[h])
+        finals[storage] = host(s.potential()[0])
+        s.close()
+    print({f"{k[0]}@{k[1]}": f"{v:.3e}" for k, v in errs.items()})
+    for v in errs.values():
+        assert v < 1e-2, errs
+    assert poisson.mean_relative_error(finals["f32"], finals["f64"]) < 1e-5

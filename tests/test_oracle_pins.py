@@ -473,3 +473,19 @@ def test_energy_of_uniform_sphere_converges_to_closed_form():
         W = core.energy(g, rho, poisson.solve_dst(g, rho, 1.0, P))
         errs.append(abs(W / (-0.6 * M * M / R) - 1.0))
     assert errs[1] < 2e-3 and errs[0] / errs[1] > 3.0, errs
+
+
+def test_mean_relative_error_eq6():
+    """Eq. 6 closed forms: a uniform relative offset eps gives |eps|; a field
+    whose relative offset is +eps on half the cells and -eps on the other half
+    gives eps; offsets 0 and 2 eps on halves give sqrt(2) eps (an RMS, not a
+    mean of magnitudes); identical fields give 0."""
+    rng = np.random.default_rng(12)
+    p = -rng.uniform(0.5, 2.0, (6, 7, 8))
+    eps = 3e-3
+    assert poisson.mean_relative_error(p * (1 + eps), p) == pytest.approx(eps, rel=1e-12)
+    sign = np.where(np.arange(p.size).reshape(p.shape) % 2 == 0, 1.0, -1.0)
+    assert poisson.mean_relative_error(p * (1 + eps * sign), p) == pytest.approx(eps, rel=1e-12)
+    two = np.where(sign > 0, 2 * eps, 0.0)
+    assert poisson.mean_relative_error(p * (1 + two), p) == pytest.approx(np.sqrt(2) * eps, rel=1e-12)
+    assert poisson.mean_relative_error(p, p) == 0.0
