@@ -68,6 +68,15 @@ def counter_traffic(kernel: str, launches_cells: int):
         return None
 
 
+def host_cpu() -> str:
+    """Model name and logical CPU count of the host, from /proc/cpuinfo."""
+    try:
+        names = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")]
+        return f"{names[0]} ({len(names)} logical CPUs)" if names else "unknown"
+    except OSError:
+        return "unknown"
+
+
 def cpu_baseline(rho_host, n, nsub, dt, phi0_host=None, gpu=None):
     """The FP64 oracle, as it stands, over one hydro step of the same workload
     (from phi0 when given, else from zero).  gpu = (phi, gx, gy, gz) of the
@@ -94,6 +103,24 @@ def cpu_baseline(rho_host, n, nsub, dt, phi0_host=None, gpu=None):
         "kind": "oracle",
         "sample": f"one hydro step ({n}^3, moments+ghosts, {nsub} substeps, gradient) in {t:.2f} s",
     }
+    # the same oracle on one thread, over a smaller sample of the workload
+    nt = core.max_threads()
+    stride = max(1, n // 256)
+    r1 = np.ascontiguousarray(r[::stride, ::stride, ::stride])
+    m = r1.shape[0]
+    g1 = Grid.cube(m)
+    o1 = Oracle(g1, lmax=4, eta=0.0)
+    core.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        o1.step(r1, 1.0, 0.4 * g1.dx, nsub)
+        o1.accel()
+        t1 = time.perf_counter() - t1
+    finally:
+        core.set_threads(nt)
+    out["one_thread"] = {"value": nsub * m ** 3 / t1 / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+                         "sample": f"one hydro step ({m}^3, the density sampled every {stride} cells) in {t1:.2f} s"}
+    out["host_cpu"] = host_cpu()
     if gpu is not None:
         rel = lambda a, b: float(np.max(np.abs(np.asarray(a, dtype=np.float64) - b)) / np.max(np.abs(b)))
         out["gpu_vs_oracle"] = {"phi": rel(gpu[0], o.potential()[0]),

@@ -51,6 +51,8 @@ def lib():
             L.orc_residual_local.argtypes = [i, i, i, d, _dp, _dp, d, d, _dp]
             L.orc_max_threads.restype = ctypes.c_int
             L.orc_max_threads.argtypes = []
+            L.orc_set_threads.restype = None
+            L.orc_set_threads.argtypes = [i]
             for f in ("orc_moments", "orc_boundary", "orc_laplacian", "orc_substeps",
                       "orc_gradient", "orc_residual", "orc_substeps_local", "orc_local_ghosts",
                       "orc_residual_local"):
@@ -62,6 +64,11 @@ def lib():
 def max_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's later parallel loops (n >= 1)."""
+    lib().orc_set_threads(int(n))
 
 
 def _p(a: np.ndarray):

@@ -528,3 +528,5 @@ void orc_residual_local(int nx, int ny, int nz, double dx, const double* phi, co
 int orc_abi_version(void) { return 1; }
 
 int orc_max_threads(void) { return omp_get_max_threads(); }
+/* threads for the following parallel loops of the calling thread (n >= 1) */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
