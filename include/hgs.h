@@ -229,6 +229,17 @@ hgs_status hgs_embed(const void* inner, int32_t nx, int32_t ny, int32_t nz, int3
 hgs_status hgs_extract(const void* outer, int32_t nx, int32_t ny, int32_t nz, int32_t ext, void* inner, int32_t dtype,
                        void* stream);
 
+/* g = -grad phi on the box [i0, i0 + bx) x [j0, j0 + by) x [k0, k0 + bz) of
+ * the interior only, written as three compact (bz, by, bx) device arrays of the
+ * storage dtype, enqueued on the context's stream.  Every value equals
+ * hgs_accel's at the same cell (same arithmetic; the box's neighbours are the
+ * grid's cells, ghosts where the box touches a face).  On an extended grid the
+ * hydrodynamics region is the box (ext, ext, ext, nx, ny, nz), which spares the
+ * gradient of the extension and the three extractions.  HGS_ERR_ARG for a NULL
+ * ctx or output, or a box that is empty or not inside the interior. */
+hgs_status hgs_accel_box(hgs_ctx* ctx, int32_t i0, int32_t j0, int32_t k0, int32_t bx, int32_t by, int32_t bz,
+                         void* gx, void* gy, void* gz);
+
 /* Bitwise copy of the raw two-level state (phi^n, phi^{n-1} interiors, device
  * (nz,ny,nx) buffers) and the previous step size, for checkpoint/resume. */
 hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev);
@@ -242,7 +253,7 @@ int32_t hgs_get_tblock(const hgs_ctx* ctx);
  * each kernel launch of the given kind, for roofline measurements:
  *   HGS_KERNEL_STENCIL  the substep launches of hgs_step (streaming or fused),
  *   HGS_KERNEL_MULTIPOLE the moment and ghost-shell launches of hgs_step,
- *   HGS_KERNEL_GRADIENT the launches of hgs_accel.
+ *   HGS_KERNEL_GRADIENT the launches of hgs_accel and hgs_accel_box.
  * hgs_timing_enable(ctx, 1) clears earlier records and starts recording;
  * 0 stops.  hgs_timing_read synchronises and returns, for one kind,
  *   out[0] launches, out[1] summed launch time in ms, out[2] algorithmic HBM

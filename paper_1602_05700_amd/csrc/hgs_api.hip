@@ -356,7 +356,7 @@ void run_mean(hgs_ctx* c, const void* rho) {
     const int nb = grid_for(n, 256, kRedBlocks);
     hipLaunchKernelGGL(k_sum_partial<S>, dim3(nb), dim3(256), 0, c->stream, static_cast<const S*>(rho), n,
                        c->red_partial);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c->stream, c->red_partial, nb, 1.0 / (double)n, c->mean);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, c->stream, c->red_partial, nb, 1.0 / (double)n, c->mean);
 }
 
 template <typename S>
@@ -407,22 +407,42 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
     }
 }
 
+// Gradient over the cells of layout W read from phi (W may be a box inside
+// the grid: the same pitch and plane with a shifted base), compact outputs.
 template <typename S>
-void run_accel(hgs_ctx* c, void* gx, void* gy, void* gz) {
+void launch_gradient(hgs_ctx* c, const S* phi, const Layout& W, void* gx, void* gy, void* gz, bool vec) {
     int zc, tx, ty, nb;
     Timed tm(c, HGS_KERNEL_GRADIENT);
-    if (use_vec<S>(c->L)) {
-        stream_dims(c->L, 64 * Vec16<S>::N, zc, tx, ty, nb);
-        hipLaunchKernelGGL((k_gradient_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream, B<S>(c, c->cur), c->L,
-                           0.5 / c->cfg.dx, zc, tx, ty, static_cast<S*>(gx), static_cast<S*>(gy),
-                           static_cast<S*>(gz));
+    if (vec) {
+        stream_dims(W, 64 * Vec16<S>::N, zc, tx, ty, nb);
+        hipLaunchKernelGGL((k_gradient_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream, phi, W, 0.5 / c->cfg.dx, zc,
+                           tx, ty, static_cast<S*>(gx), static_cast<S*>(gy), static_cast<S*>(gz));
     } else {
-        stream_dims(c->L, SBX, zc, tx, ty, nb);
-        hipLaunchKernelGGL((k_gradient<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream, B<S>(c, c->cur),
-                           c->L, 0.5 / c->cfg.dx, zc, tx, ty, static_cast<S*>(gx), static_cast<S*>(gy),
-                           static_cast<S*>(gz));
+        stream_dims(W, SBX, zc, tx, ty, nb);
+        hipLaunchKernelGGL((k_gradient<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream, phi, W,
+                           0.5 / c->cfg.dx, zc, tx, ty, static_cast<S*>(gx), static_cast<S*>(gy), static_cast<S*>(gz));
     }
-    tm.end(4.0 * sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz, 0.0);
+    tm.end(4.0 * sizeof(S) * (double)W.nx * W.ny * W.nz, 0.0);
+}
+
+template <typename S>
+void run_accel(hgs_ctx* c, void* gx, void* gy, void* gz) {
+    launch_gradient<S>(c, B<S>(c, c->cur), c->L, gx, gy, gz, use_vec<S>(c->L));
+}
+
+// The box [i0, i0 + bx) x [j0, j0 + by) x [k0, k0 + bz) of the interior as a
+// layout of its own: its cells are those of the grid, so the stencil reads
+// the grid's neighbours (ghosts where the box touches a face).  16-byte lanes
+// need the box to start and end on whole vectors along x.
+template <typename S>
+void run_accel_box(hgs_ctx* c, const int* box, void* gx, void* gy, void* gz) {
+    Layout W = c->L;
+    W.nx = box[3];
+    W.ny = box[4];
+    W.nz = box[5];
+    const S* phi = B<S>(c, c->cur) + ((int64_t)box[2] * W.plane + (int64_t)box[1] * W.pitch + box[0]);
+    const bool vec = box[0] % Vec16<S>::N == 0 && use_vec<S>(W);
+    launch_gradient<S>(c, phi, W, gx, gy, gz, vec);
 }
 
 template <typename S>
@@ -531,7 +551,7 @@ void run_speed(hgs_ctx* c, const void* cs, const void* vx, const void* vy, const
     hipLaunchKernelGGL(k_speed_partial<S>, dim3(nb), dim3(256), 0, c->stream, static_cast<const S*>(cs),
                        static_cast<const S*>(vx), static_cast<const S*>(vy), static_cast<const S*>(vz), n,
                        c->red_partial);
-    hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(64), 0, c->stream, c->red_partial, nb, c->red_out);
+    hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, c->red_partial, nb, c->red_out);
 }
 
 // W = 1/2 sum rho phi dx^3 into red_out[0]
@@ -541,7 +561,7 @@ void run_energy(hgs_ctx* c, const void* rho) {
     hipLaunchKernelGGL(k_dot_partial<S>, dim3(nb), dim3(256), 0, c->stream, static_cast<const S*>(rho),
                        B<S>(c, c->cur), c->L, c->red_partial);
     const double dv = c->cfg.dx * c->cfg.dx * c->cfg.dx;
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, c->stream, c->red_partial, nb, 0.5 * dv, c->red_out);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, c->stream, c->red_partial, nb, 0.5 * dv, c->red_out);
 }
 
 hgs_status read_out(hgs_ctx* c, double* dst, int n, const char* what) {
@@ -765,6 +785,20 @@ hgs_status hgs_accel(hgs_ctx* ctx, void* gx, void* gy, void* gz) {
     return launch_check(ctx, "hgs_accel");
 }
 
+hgs_status hgs_accel_box(hgs_ctx* ctx, int32_t i0, int32_t j0, int32_t k0, int32_t bx, int32_t by, int32_t bz,
+                         void* gx, void* gy, void* gz) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!gx || !gy || !gz) return fail(ctx, HGS_ERR_ARG, "gx, gy and gz must be non-NULL");
+    const Layout& L = ctx->L;
+    if (i0 < 0 || j0 < 0 || k0 < 0 || bx < 1 || by < 1 || bz < 1 || (int64_t)i0 + bx > L.nx ||
+        (int64_t)j0 + by > L.ny || (int64_t)k0 + bz > L.nz)
+        return fail(ctx, HGS_ERR_ARG, "the box must be non-empty and inside the interior");
+    (void)hipGetLastError();
+    const int box[6] = {i0, j0, k0, bx, by, bz};
+    DISPATCH(ctx, run_accel_box, ctx, box, gx, gy, gz);
+    return launch_check(ctx, "hgs_accel_box");
+}
+
 hgs_status hgs_set_state(hgs_ctx* ctx, const void* phi, const void* phidot, double dt) {
     if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
     if (!phi) return fail(ctx, HGS_ERR_ARG, "phi is NULL");
@@ -918,14 +952,15 @@ hgs_status hgs_embed(const void* inner, int32_t nx, int32_t ny, int32_t nz, int3
     hgs_status s = ext_check(inner, outer, nx, ny, nz, ext, dtype);
     if (s != HGS_OK) return s;
     (void)hipGetLastError();
-    const int64_t n = ((int64_t)nx + 2 * ext) * ((int64_t)ny + 2 * ext) * ((int64_t)nz + 2 * ext);
+    // one wave per outer row, four rows per workgroup
+    const dim3 grid((ny + 2 * ext + 3) / 4, nz + 2 * ext);
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (dtype == HGS_F32)
-        hipLaunchKernelGGL(k_embed<float>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const float*>(inner), nx,
-                           ny, nz, ext, static_cast<float*>(outer));
+        hipLaunchKernelGGL(k_embed<float>, grid, dim3(64, 4), 0, st, static_cast<const float*>(inner), nx, ny, nz,
+                           ext, static_cast<float*>(outer));
     else
-        hipLaunchKernelGGL(k_embed<double>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const double*>(inner),
-                           nx, ny, nz, ext, static_cast<double*>(outer));
+        hipLaunchKernelGGL(k_embed<double>, grid, dim3(64, 4), 0, st, static_cast<const double*>(inner), nx, ny, nz,
+                           ext, static_cast<double*>(outer));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? HGS_OK : fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_embed: ") + hipGetErrorString(e));
 }
@@ -935,14 +970,15 @@ hgs_status hgs_extract(const void* outer, int32_t nx, int32_t ny, int32_t nz, in
     hgs_status s = ext_check(outer, inner, nx, ny, nz, ext, dtype);
     if (s != HGS_OK) return s;
     (void)hipGetLastError();
-    const int64_t n = (int64_t)nx * ny * nz;
+    // one wave per inner row, four rows per workgroup
+    const dim3 grid((ny + 3) / 4, nz);
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (dtype == HGS_F32)
-        hipLaunchKernelGGL(k_extract<float>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const float*>(outer), nx,
-                           ny, nz, ext, static_cast<float*>(inner));
+        hipLaunchKernelGGL(k_extract<float>, grid, dim3(64, 4), 0, st, static_cast<const float*>(outer), nx, ny, nz,
+                           ext, static_cast<float*>(inner));
     else
-        hipLaunchKernelGGL(k_extract<double>, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const double*>(outer),
-                           nx, ny, nz, ext, static_cast<double*>(inner));
+        hipLaunchKernelGGL(k_extract<double>, grid, dim3(64, 4), 0, st, static_cast<const double*>(outer), nx, ny,
+                           nz, ext, static_cast<double*>(inner));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? HGS_OK
                            : fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_extract: ") + hipGetErrorString(e));

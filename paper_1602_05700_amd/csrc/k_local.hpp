@@ -75,26 +75,63 @@ __global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int
     nxt[pg] = (S)v;
 }
 
-// Sum of a compact field in FP64: per-workgroup partials (grid-stride, fixed
-// order), then one thread adds them in order and scales.
-template <typename S>
-__global__ __launch_bounds__(256) void k_sum_partial(const S* __restrict__ f, int64_t n, double* __restrict__ partial) {
-    __shared__ double red[4];
-    double acc = 0.0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        acc += (double)f[t];
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+// Block-wide FP64 sum over 256 threads in a fixed order (wave butterflies,
+// then the four waves pairwise); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum_256(double v, double* red4) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    return (red4[0] + red4[1]) + (red4[2] + red4[3]);
 }
 
-__global__ void k_sum_final(const double* __restrict__ partial, int nb, double scale, double* __restrict__ out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < nb; ++i) s += partial[i];
-        *out = s * scale;
+// Sum of a compact field in FP64: per-workgroup partials, then one workgroup
+// adds them.  Threads take 16-byte vectors of the field (when it is 16-byte
+// aligned) in a grid-stride loop with four independent loads in flight, and
+// the scalar tail; the order of every addition is fixed, so the result is the
+// same from run to run.
+template <typename S>
+__global__ __launch_bounds__(256) void k_sum_partial(const S* __restrict__ f, int64_t n, double* __restrict__ partial) {
+    constexpr int N = 16 / sizeof(S);
+    typedef S VT __attribute__((ext_vector_type(N)));
+    __shared__ double red[4];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(f) & 15) == 0) {
+        const VT* fv = reinterpret_cast<const VT*>(f);
+        const int64_t nv = n / N;
+        int64_t t = t0;
+        for (; t + 3 * stride < nv; t += 4 * stride) {
+            VT v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = fv[t + u * stride];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int e = 0; e < N; ++e) a[u] += (double)v[u][e];
+        }
+        for (; t < nv; t += stride) {
+            const VT v = fv[t];
+#pragma unroll
+            for (int e = 0; e < N; ++e) a[0] += (double)v[e];
+        }
+        done = nv * N;
     }
+    for (int64_t t = done + t0; t < n; t += stride) a[1] += (double)f[t];
+    const double s = block_sum_256((a[0] + a[1]) + (a[2] + a[3]), red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out = scale * (sum of the nb partials): thread t adds partials t, t + 256,
+// ... in order, then the fixed block tree.  Launched as one workgroup of 256.
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ partial, int nb, double scale,
+                                                   double* __restrict__ out) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) v += partial[i];
+    const double s = block_sum_256(v, red);
+    if (threadIdx.x == 0) *out = s * scale;
 }
 
 }  // namespace hgs
@@ -103,19 +140,59 @@ namespace hgs {
 
 // Largest signal speed c_s + |v| over the cells (FP64) and a non-finite flag,
 // per workgroup: partial[2 b] = max, partial[2 b + 1] = 1 if any value was not
-// finite.  vx, vy, vz nullable (0).
+// finite.  vx, vy, vz nullable (0).  16-byte vectors of all four fields when
+// they are all 16-byte aligned (two vectors per field in flight per thread),
+// then the scalar tail; max is exact, so the split does not change the result.
+__device__ __forceinline__ void speed_acc(double s, double a, double b, double c, double& m, double& bad) {
+    const double v = s + sqrt(a * a + b * b + c * c);
+    if (!isfinite(v)) bad = 1.0;
+    else m = fmax(m, v);
+}
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_speed_partial(const S* __restrict__ cs, const S* __restrict__ vx,
                                                        const S* __restrict__ vy, const S* __restrict__ vz, int64_t n,
                                                        double* __restrict__ partial) {
+    constexpr int N = 16 / sizeof(S);
+    typedef S VT __attribute__((ext_vector_type(N)));
     __shared__ double red[4][2];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double m = 0.0, bad = 0.0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const double a = vx ? (double)vx[t] : 0.0, b = vy ? (double)vy[t] : 0.0, c = vz ? (double)vz[t] : 0.0;
-        const double v = (double)cs[t] + sqrt(a * a + b * b + c * c);
-        if (!isfinite(v)) bad = 1.0;
-        else m = fmax(m, v);
+    const uintptr_t mis = (reinterpret_cast<uintptr_t>(cs) | reinterpret_cast<uintptr_t>(vx) |
+                           reinterpret_cast<uintptr_t>(vy) | reinterpret_cast<uintptr_t>(vz)) & 15;
+    int64_t done = 0;
+    if (mis == 0) {
+        const int64_t nv = n / N;
+        const VT zero = (VT)(S)0;
+        const VT* pc = reinterpret_cast<const VT*>(cs);
+        const VT* px = reinterpret_cast<const VT*>(vx);
+        const VT* py = reinterpret_cast<const VT*>(vy);
+        const VT* pz = reinterpret_cast<const VT*>(vz);
+        for (int64_t t = t0; t < nv; t += 2 * stride) {
+            // the second vector repeats the first past the end: max and the
+            // flag are idempotent, and the loads stay unconditional
+            const bool two = t + stride < nv;
+            VT c[2], x[2], y[2], z[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int64_t q = (u == 0 || two) ? t + u * stride : t;
+                c[u] = pc[q];
+                x[u] = px ? px[q] : zero;
+                y[u] = py ? py[q] : zero;
+                z[u] = pz ? pz[q] : zero;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int e = 0; e < N; ++e)
+                    speed_acc((double)c[u][e], (double)x[u][e], (double)y[u][e], (double)z[u][e], m, bad);
+        }
+        done = nv * N;
     }
+    for (int64_t t = done + t0; t < n; t += stride)
+        speed_acc((double)cs[t], vx ? (double)vx[t] : 0.0, vy ? (double)vy[t] : 0.0, vz ? (double)vz[t] : 0.0,
+                     m, bad);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         m = fmax(m, __shfl_xor(m, o, 64));
@@ -131,36 +208,48 @@ __global__ __launch_bounds__(256) void k_speed_partial(const S* __restrict__ cs,
             fmax(fmax(red[0][threadIdx.x], red[1][threadIdx.x]), fmax(red[2][threadIdx.x], red[3][threadIdx.x]));
 }
 
-__global__ void k_speed_final(const double* __restrict__ partial, int nb, double* __restrict__ out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double m = 0.0, bad = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            m = fmax(m, partial[2 * i]);
-            bad = fmax(bad, partial[2 * i + 1]);
-        }
-        out[0] = m;
-        out[1] = bad;
+// out[0] = max of the partial maxima, out[1] = the non-finite flag.  One
+// workgroup of 256: thread t takes partials t, t + 256, ..., then the block.
+__global__ __launch_bounds__(256) void k_speed_final(const double* __restrict__ partial, int nb,
+                                                     double* __restrict__ out) {
+    __shared__ double red[4][2];
+    double m = 0.0, bad = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        m = fmax(m, partial[2 * i]);
+        bad = fmax(bad, partial[2 * i + 1]);
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o, 64));
+        bad = fmax(bad, __shfl_xor(bad, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = m;
+        red[threadIdx.x >> 6][1] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) out[threadIdx.x] = fmax(fmax(red[0][threadIdx.x], red[1][threadIdx.x]),
+                                                 fmax(red[2][threadIdx.x], red[3][threadIdx.x]));
 }
 
 // sum over interior cells of rho * phi (phi in the padded layout), FP64
-// partials per workgroup; the caller scales by dx^3 / 2 for W.
+// partials per workgroup; the caller scales by dx^3 / 2 for W.  Each wave
+// walks whole rows (rows w, w + 4 G, ... of workgroup b with G workgroups).
 template <typename S>
 __global__ __launch_bounds__(256) void k_dot_partial(const S* __restrict__ rho, const S* __restrict__ phi, Layout L,
                                                      double* __restrict__ partial) {
     __shared__ double red[4];
     double acc = 0.0;
-    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t % L.nx);
-        const int j = (int)((t / L.nx) % L.ny);
-        const int k = (int)(t / ((int64_t)L.nx * L.ny));
-        acc += (double)rho[t] * (double)phi[L.idx(i, j, k)];
+    const int64_t rows = (int64_t)L.ny * L.nz;
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gridDim.x * 4) {
+        const int j = (int)(r % L.ny), k = (int)(r / L.ny);
+        const S* pr = rho + r * L.nx;
+        const S* pp = phi + L.idx(0, j, k);
+        for (int i = lane; i < L.nx; i += 64) acc += (double)pr[i] * (double)pp[i];
     }
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    const double s = block_sum_256(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 }  // namespace hgs
@@ -171,31 +260,35 @@ namespace hgs {
 // than the hydrodynamics region, the extension taken as vacuum).  Compact
 // fields: inner (nz, ny, nx) <-> outer (nz + 2e, ny + 2e, nx + 2e).
 // k_embed writes every outer cell (inner values in the centre, 0 around).
+// Both kernels give each wave one row (workgroups of 64 x 4 rows, grid
+// (rows / 4, planes)), so no per-element index division is needed.
 template <typename S>
 __global__ __launch_bounds__(256) void k_embed(const S* __restrict__ inner, int nx, int ny, int nz, int e,
                                                S* __restrict__ outer) {
-    const int ox = nx + 2 * e, oy = ny + 2 * e, oz = nz + 2 * e;
-    const int64_t total = (int64_t)ox * oy * oz;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t % ox) - e;
-        const int j = (int)((t / ox) % oy) - e;
-        const int k = (int)(t / ((int64_t)ox * oy)) - e;
-        const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
-        outer[t] = in ? inner[((int64_t)k * ny + j) * nx + i] : (S)0;
+    const int ox = nx + 2 * e, oy = ny + 2 * e;
+    const int j = blockIdx.x * 4 + threadIdx.y;
+    const int k = blockIdx.y;
+    if (j >= oy) return;
+    S* dst = outer + ((int64_t)k * oy + j) * ox;
+    const int jj = j - e, kk = k - e;
+    if (jj < 0 || jj >= ny || kk < 0 || kk >= nz) {
+        for (int i = threadIdx.x; i < ox; i += 64) dst[i] = (S)0;
+        return;
     }
+    const S* src = inner + ((int64_t)kk * ny + jj) * nx;
+    for (int i = threadIdx.x; i < ox; i += 64) dst[i] = (i >= e && i < e + nx) ? src[i - e] : (S)0;
 }
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_extract(const S* __restrict__ outer, int nx, int ny, int nz, int e,
                                                  S* __restrict__ inner) {
     const int ox = nx + 2 * e, oy = ny + 2 * e;
-    const int64_t total = (int64_t)nx * ny * nz;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t % nx);
-        const int j = (int)((t / nx) % ny);
-        const int k = (int)(t / ((int64_t)nx * ny));
-        inner[t] = outer[((int64_t)(k + e) * oy + (j + e)) * ox + (i + e)];
-    }
+    const int j = blockIdx.x * 4 + threadIdx.y;
+    const int k = blockIdx.y;
+    if (j >= ny) return;
+    const S* src = outer + ((int64_t)(k + e) * oy + (j + e)) * ox + e;
+    S* dst = inner + ((int64_t)k * ny + j) * nx;
+    for (int i = threadIdx.x; i < nx; i += 64) dst[i] = src[i];
 }
 
 }  // namespace hgs

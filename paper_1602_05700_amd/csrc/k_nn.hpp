@@ -593,12 +593,18 @@ __global__ __launch_bounds__(256) void k_compose(const float* __restrict__ phi_c
     }
 }
 
-__global__ void k_sum_partials(const double* __restrict__ partial, int n, double* __restrict__ out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += partial[i];
-        *out = s;
-    }
+// out = the sum of n partials in a fixed order: thread t adds partials t,
+// t + 256, ..., then the wave butterflies and the four waves pairwise.  One
+// workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int n,
+                                                      double* __restrict__ out) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += partial[i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Adam with bias correction; FP32 master parameters, optional bf16 copy.

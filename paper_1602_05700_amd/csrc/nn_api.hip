@@ -134,7 +134,7 @@ hgs_status hgs_nn_mse(const float* out, const float* target, int32_t B, int32_t 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const float inv = (float)(1.0 / ((double)B * C * nvox));
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, out, target, B, C, nvox, inv, grad, partials);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, partials, nb, loss_dev);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, nb, loss_dev);
     return nlaunched("hgs_nn_mse");
 }
 
@@ -154,7 +154,7 @@ hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32
                        scratch);
     hipLaunchKernelGGL(k_lapmse, dim3(nb), dim3(256), 0, st, out, target, scratch, B, C, ch, nz, ny, nx, w, inv, grad,
                        partials);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, partials, nb, loss_dev);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, nb, loss_dev);
     return nlaunched("hgs_nn_lapmse");
 }
 

@@ -60,6 +60,7 @@ _SIGS = {
     "hgs_validate_step": (_i32, [_CFG, _vp, _dbl, _dbl, _i32]),
     "hgs_potential": (_i32, [_vp, _vp, _vp]),
     "hgs_accel": (_i32, [_vp, _vp, _vp, _vp]),
+    "hgs_accel_box": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
     "hgs_set_state": (_i32, [_vp, _vp, _vp, _dbl]),
     "hgs_set_boundary": (_i32, [_vp, _vp]),
     "hgs_get_boundary": (_i32, [_vp, _vp]),
@@ -237,6 +238,15 @@ class Solver:
         _check(_lib.hgs_accel(self._h, *(t.data_ptr() for t in g)), self._h)
         return tuple(g)
 
+    def accel_box(self, start, shape, out=None):
+        """g on the box of the interior that starts at cell start = (k0, j0, i0)
+        and has shape (bz, by, bx), as three compact arrays of that shape."""
+        (k0, j0, i0), shape = start, tuple(int(v) for v in shape)
+        g = [self._new(shape) for _ in range(3)] if out is None else [self._need(t, shape) for t in out]
+        _check(_lib.hgs_accel_box(self._h, int(i0), int(j0), int(k0), shape[2], shape[1], shape[0],
+                                  *(t.data_ptr() for t in g)), self._h)
+        return tuple(g)
+
     def set_state(self, phi, phidot, dt: float) -> None:
         self._need(phi)
         self._need(phidot)
@@ -349,7 +359,8 @@ class ExtendedSolver:
     """A solver on a grid wider than the hydrodynamics region by `ext` cells on
     every side, the extension treated as vacuum (Sec. 4: a cheap way to move a
     local boundary away from the matter).  rho, phi and g are exchanged on the
-    hydrodynamics region (nz, ny, nx) only; hgs_embed / hgs_extract move them."""
+    hydrodynamics region (nz, ny, nx) only; hgs_embed / hgs_extract move rho
+    and phi, and g comes from hgs_accel_box on that region."""
 
     def __init__(self, shape, ext: int, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, bc: str = "outgoing",
                  **kw):
@@ -392,8 +403,11 @@ class ExtendedSolver:
         phi, pd = self.solver.potential(with_phidot)
         return self.extract(phi), (self.extract(pd) if pd is not None else None)
 
-    def accel(self):
-        return tuple(self.extract(g) for g in self.solver.accel())
+    def accel(self, out=None):
+        """g on the hydrodynamics region only (the gradient of the extension
+        is never computed)."""
+        e = self.ext
+        return self.solver.accel_box((e, e, e), self.inner, out)
 
     def residual(self, rho) -> np.ndarray:
         """Residual over the whole wider grid (rho embedded)."""

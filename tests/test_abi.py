@@ -165,6 +165,7 @@ def test_embed_extract_host_checks():
     assert L.hgs_embed(a, 4, 4, 4, 1, a, 9, None) == hgs.HGS_ERR_ARG
     assert L.hgs_extract(a, 8000, 4, 4, 200, a, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
     assert L.hgs_extract(a, 4, 4, 4, 1, None, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_accel_box(None, 0, 0, 0, 1, 1, 1, a, a, a) == hgs.HGS_ERR_ARG
 
 
 def test_warmstart_criterion_checks():

@@ -33,6 +33,33 @@ def test_max_signal_speed(gpu_lib, storage):
         s.max_signal_speed(to_dev(cs), [to_dev(bad), to_dev(v[1]), to_dev(v[2])])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("shape,offset", [((5, 7, 9), 0), ((5, 7, 9), 1), ((161, 161, 131), 0), ((64, 64, 66), 3)])
+def test_max_signal_speed_vector_and_tail(gpu_lib, storage, shape, offset):
+    """The reduction's 16-byte path, its scalar tail (cell counts that are not
+    whole vectors), the scalar path for fields that are not 16-byte aligned
+    (offset views), and grids large enough for the unrolled loop."""
+    import torch
+
+    rng = np.random.default_rng(32)
+    dt = npdt(storage)
+    n = int(np.prod(shape))
+    f = [rng.uniform(0.1, 1.0, n).astype(dt)] + [rng.normal(0, 0.5, n).astype(dt) for _ in range(3)]
+    f[2][n // 3] = 7.5  # a single peak far from either end
+
+    def dev(a):
+        buf = torch.zeros(n + offset, dtype=torch.float64 if storage == "f64" else torch.float32, device="cuda")
+        buf[offset:] = torch.from_numpy(a).to("cuda")
+        return buf[offset:].view(shape)
+
+    s = solver(gpu_lib, shape, storage=storage)
+    want = np.max(f[0].astype(np.float64) + np.sqrt(sum(a.astype(np.float64) ** 2 for a in f[1:])))
+    # the GPU may contract a*a + b*b + c*c into fused multiply-adds
+    assert s.max_signal_speed(dev(f[0]), [dev(a) for a in f[1:]]) == pytest.approx(want, rel=1e-15)
+    want2 = np.max(f[0].astype(np.float64) + np.abs(f[2].astype(np.float64)))
+    assert s.max_signal_speed(dev(f[0]), [None, dev(f[2]), None]) == pytest.approx(want2, rel=1e-15)
+
+
 def test_hydro_step_is_the_sub_cycled_step(gpu_lib):
     """hgs_hydro_step = hgs_step(rho, k_g vmax, dt_h / nsub, nsub) with
     dt_h = C_h dx / vmax and nsub = ceil(k_g C_h / C_g), bitwise."""

@@ -76,3 +76,22 @@ def test_robin_error_falls_with_extension(gpu_lib):
     assert errs[0] > errs[1] > errs[2], errs
     prod = [a * b for a, b in zip(errs, zones)]
     assert max(prod) / min(prod) < 1.6, (errs, prod)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("shape,e", [((3, 5, 7), 0), ((3, 5, 7), 1), ((9, 4, 70), 33), ((20, 18, 129), 2)])
+def test_embed_extract_round_trip(gpu_lib, storage, shape, e):
+    """hgs_embed writes every outer cell (zeros around the region), and
+    hgs_extract returns the region bitwise, for rows shorter and longer than
+    a wave and extensions wider than the region."""
+    import torch
+
+    nz, ny, nx = shape
+    rng = np.random.default_rng(41)
+    a = rng.normal(size=shape).astype(np.float64 if storage == "f64" else np.float32)
+    g = grid_of(shape)
+    s = gpu_lib.ExtendedSolver(shape, e, x0=(g.x0, g.y0, g.z0), dx=g.dx, storage=storage)
+    outer = torch.full(tuple(v + 2 * e for v in shape), float("nan"), dtype=s.dtype, device="cuda")
+    s.embed(to_dev(a), outer)
+    assert np.array_equal(host(outer), np.pad(a.astype(np.float64), e))
+    assert np.array_equal(host(s.extract(outer)), a)

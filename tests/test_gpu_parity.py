@@ -204,6 +204,27 @@ def test_ghosts_follow_every_buffer_rotation(gpu_lib, storage):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_accel_box_equals_accel_on_the_box(gpu_lib, storage):
+    """hgs_accel_box gives hgs_accel's values on the box, bitwise: boxes that
+    start and end on whole 16-byte vectors along x (vector kernel) or not
+    (scalar kernel), touch the faces, cover the grid, or hold one cell."""
+    shape = (23, 29, 40)
+    g = grid_of(shape)
+    s = solver(gpu_lib, shape, storage=storage)
+    s.step(to_dev(dens(shape, 21, storage)), 1.0, 0.3 * g.dx, 6)
+    full = [host(a) for a in s.accel()]
+    boxes = [((0, 0, 0), shape), ((1, 2, 3), (10, 11, 12)), ((5, 3, 4), (7, 9, 8)), ((3, 9, 32), (20, 20, 8)),
+             ((22, 28, 39), (1, 1, 1)), ((0, 0, 0), (23, 29, 4)), ((4, 6, 8), (15, 17, 24))]
+    for (k0, j0, i0), (bz, by, bx) in boxes:
+        got = [host(a) for a in s.accel_box((k0, j0, i0), (bz, by, bx))]
+        for a, b in zip(got, full):
+            assert np.array_equal(a, b[k0:k0 + bz, j0:j0 + by, i0:i0 + bx]), ((k0, j0, i0), (bz, by, bx))
+    for bad in (((0, 0, 0), (24, 1, 1)), ((0, 0, -1), (1, 1, 1)), ((0, 0, 39), (1, 1, 2)), ((0, 0, 0), (0, 1, 1))):
+        with pytest.raises((gpu_lib.HGSError, ValueError)):
+            s.accel_box(*bad)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_set_state_then_step(gpu_lib, storage):
     shape = (20, 18, 22)
     g = grid_of(shape)
