@@ -70,6 +70,7 @@ thread_local std::string g_err;
 constexpr int kMaxN = 8192;
 constexpr size_t kAlign = 256;
 constexpr int kRedBlocks = 1024;
+constexpr int kMomMinZ = 32;  // fewest z planes per moment chunk (when nz allows)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -153,14 +154,18 @@ Plan make_plan(const hgs_config* cfg) {
     Layout L = make_layout(cfg->nx, cfg->ny, cfg->nz, es);
     p.buf_bytes = align_up((size_t)L.total * es, kAlign);
     // moments: 64 x 4 lanes over (x, y) columns (N columns per lane when
-    // vectorised); split z so that there are >= 2048 workgroups when possible
+    // vectorised); split z towards >= 2048 workgroups, but keep at least
+    // kMomMinZ planes per chunk: every lane ends its chunk with the harmonics
+    // of its columns (about 150 FP64 operations each) and a 25-value block
+    // reduction, which short chunks do not amortise (256^3 FP32 with 8-plane
+    // chunks read rho at 1.7 TB/s)
     const int vec = 16 / es;
     p.mom_vec = cfg->nx % vec == 0;
     const int colw = p.mom_vec ? 64 * vec : 64;
     p.mom_tx = (cfg->nx + colw - 1) / colw;
     p.mom_ty = (cfg->ny + 3) / 4;
     int cols = p.mom_tx * p.mom_ty;
-    int zsplit = std::max(1, std::min(cfg->nz, (2048 + cols - 1) / cols));
+    int zsplit = std::max(1, std::min(cfg->nz / kMomMinZ, (2048 + cols - 1) / cols));
     p.mom_zc = (cfg->nz + zsplit - 1) / zsplit;
     p.mom_blocks = cols * ((cfg->nz + p.mom_zc - 1) / p.mom_zc);
     size_t off = 4 * p.buf_bytes;

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int
 }
 
 // Block-wide FP64 sum over 256 threads in a fixed order (wave butterflies,
-// then the four waves pairwise); the result is valid in thread 0.
+// then the four waves pairwise); every thread returns the same sum.
 __device__ __forceinline__ double block_sum_256(double v, double* red4) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
