@@ -168,7 +168,8 @@ def run_configs(dev):
     as in Eq. 2 and critically damped) and the 256^3 rotating 8-blob mixture
     (seed 0, speed 0.1 c_g at radius 1, lmax 4, 4 substeps per hydro step,
     250 hydro steps, FP64 and FP32 storage, moments + ghosts + substeps +
-    gradient timed; 64 rotated densities generated beforehand and cycled)."""
+    gradient timed; 64 rotated densities generated beforehand and cycled).
+    Each run takes the fused depth the library's autotuner picks for it."""
     import math
 
     import torch
@@ -183,9 +184,12 @@ def run_configs(dev):
     rho = torch.from_numpy(workloads.sphere_density(n, 0.25)).to(dev)
     lam = 3 * (4 / dx ** 2) * math.sin(math.pi / (2 * (n + 1))) ** 2  # slowest Dirichlet mode
     for label, eta in (("eta_0", 0.0), ("eta_critical", 2.0 * math.sqrt(lam))):
-        s = hgs.Solver(n, storage="f64", lmax=0, eta=eta, device=dev)
+        # fused depth by the library's autotuner (timed on 8-substep steps):
+        # at 64^3 a fused launch is bound by its pipeline fill, not by HBM
+        tb, _ = hgs.autotune(n, rho, 1.0, dt, 8, storage="f64", lmax=0, eta=eta, device=dev)
+        s = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, device=dev)
         s.step(rho, 1.0, dt, 8)  # warm-up
-        s2 = hgs.Solver(n, storage="f64", lmax=0, eta=eta, device=dev)
+        s2 = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, device=dev)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s2.stream)
@@ -194,7 +198,8 @@ def run_configs(dev):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         out.setdefault("sphere_64_f64", {})[label] = {
-            "substeps": 2000, "ms": round(ms, 3), "Gcell_updates_per_s": round(n ** 3 * 2000 / (ms / 1e3) / 1e9, 2),
+            "substeps": 2000, "tblock": tb, "ms": round(ms, 3),
+            "Gcell_updates_per_s": round(n ** 3 * 2000 / (ms / 1e3) / 1e9, 2),
             "R_f": float(s2.residual(rho)[1])}
         s.close()
         s2.close()
@@ -204,7 +209,8 @@ def run_configs(dev):
     blobs = workloads.blob_params(0, 8)
     for storage, tdt in (("f64", torch.float64), ("f32", torch.float32)):
         rhos = [workloads.blob_density_torch(n, blobs.rotated(0.1 * nsub * dt * h), dev, tdt) for h in range(64)]
-        s = hgs.Solver(n, storage=storage, lmax=4, eta=0.0, device=dev)
+        tb, _ = hgs.autotune(n, rhos[0], 1.0, dt, nsub, storage=storage, lmax=4, eta=0.0, device=dev)
+        s = hgs.Solver(n, storage=storage, lmax=4, eta=0.0, tblock=tb, device=dev)
         g = [torch.empty((n, n, n), dtype=tdt, device=dev) for _ in range(3)]
         for h in range(3):
             s.step(rhos[h], 1.0, dt, nsub)
@@ -524,6 +530,21 @@ def main():
             "gradient": round(gr["ms"] / K * 1e3, 1),
         },
     }
+    # the timed block again, five times, for its run-to-run spread (same
+    # densities in the same order; the work does not depend on the values)
+    reps = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for h in range(K):
+            s.step(rhos[W + h], c_g, dt, nsub)
+            s.accel(out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(round(updates / (e0.elapsed_time(e1) / 1e3) / 1e9, 3))
+    line["repeat_blocks"] = {"blocks": len(reps), "steps_each": K, "Gcell_updates_per_s": reps,
+                             "median": sorted(reps)[len(reps) // 2]}
+    log(f"[bench] five more blocks of {K} hydro steps: {reps} Gcell-updates/s")
     del rhos
     if not args.no_batched:
         log("[bench] batched: 64 uneven grids, 500 substeps")
