@@ -524,6 +524,34 @@ def test_batch_against_oracle(gpu_lib):
         compare_state(g, o, "f64", F64_TOL)
 
 
+@pytest.mark.timeout(900)
+def test_batch_full_config_sampled_grids(gpu_lib):
+    """The benchmarked batch at its full size and in the launch configuration
+    the benchmark times: 64 uneven grids (N in 32..160, seed 2), FP32 storage,
+    lmax 4, one hydro step of 500 substeps at the default fused depth with
+    graph replay.  Four sampled grids (the smallest, the largest and two in
+    between) against the FP64 oracle over every cell."""
+    import torch
+
+    spec = workloads.batch_spec(seed=2, count=64)
+    rhos = [workloads.blob_density_torch(n, workloads.blob_params(sd, k), "cuda", torch.float32)
+            for n, k, sd in zip(spec.sizes, spec.nblobs, spec.seeds)]
+    b = gpu_lib.Batch(list(spec.sizes), storage="f32", lmax=4, eta=0.0)
+    dts = [0.4 * 2.0 / n for n in spec.sizes]
+    b.step(rhos, 1.0, dts, 500)
+    assert b.used_graph
+    sizes = np.asarray(spec.sizes)
+    order = np.argsort(sizes, kind="stable")
+    picks = [int(order[0]), int(order[-1]), int(order[len(order) // 3]), int(order[2 * len(order) // 3])]
+    assert len(set(picks)) == 4
+    print("sampled grids", [(i, spec.sizes[i]) for i in picks], flush=True)
+    for i in picks:
+        n = spec.sizes[i]
+        o = Oracle(Grid.cube(n), lmax=4, eta=0.0)
+        o.step(host(rhos[i]), 1.0, dts[i], 500)
+        compare_state(b.grids[i], o, "f32", F32_TOL)
+
+
 def test_batch_rejects_bad_input(gpu_lib):
     with pytest.raises(gpu_lib.HGSError):
         gpu_lib.Batch([(8, 8, 10)], storage="f32")  # nx not a multiple of 4
