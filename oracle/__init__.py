@@ -48,6 +48,14 @@ arXiv:1602.05700), and what pins it (tests/test_oracle_pins.py):
   potential) and brute-force sums used as pins.
 * ``nn.py`` -- FP64 3D convolution network pieces (forward and backward) for the
   learned warm start; pinned by central finite differences.
+* ``nested.py`` -- a coarse outer level of twice the cell size around the grid
+  (Sec. 4 names nested grids as a way to move the boundary out): 2x2x2 means
+  as the coarse source, trilinear interpolation of the coarse potential at the
+  fine ghost centres.  Pinned by (tests/test_oracle_nested.py): exactness of
+  the interpolation on affine fields, mass conservation of the source, the
+  damped iteration reaching the composite steady state of a sparse Robin solve
+  and a DST-I solve, and the error against the free-space potential falling
+  as the coarse level extends further.
 
 Parity unpinned: none of the paper's own numerical results can be compared,
 because the paper prints no worked example, table of potentials or figure data
