@@ -243,10 +243,14 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
     """Throughput of the parts built beyond the multipole path, at 256^3 FP32
     on the same 8-blob density (eta = 0, dt = 0.4 dx): the local boundaries
     (one substep per launch plus a ghost launch), the extended grid (32 vacuum
-    cells on every side, outgoing boundary, rho embedded and g extracted every
-    hydro step) and the hydro-coupled driver (signal-speed reduction over
-    c_s and v, k_g = 5, Courant numbers 0.3: 5 substeps per hydro step).  Each
-    entry: ms per hydro step (step + gradient) and cell updates per second."""
+    cells on every side, outgoing boundary, rho embedded every hydro step, g on
+    the hydrodynamics region; updates counted over the whole wider grid), the
+    nested coarse outer level (Robin at the coarse faces, 16 or 64 coarse
+    cells beyond the fine grid; coarse source, coarse substeps, interpolated
+    ghosts and the fine substeps at the fused depth; fine updates counted) and
+    the hydro-coupled driver (signal-speed reduction over c_s and v, k_g = 5,
+    Courant numbers 0.3: 5 substeps per hydro step).  Each entry: ms per
+    hydro step (step + gradient) and cell updates per second."""
     import torch
 
     import workloads
@@ -280,6 +284,11 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
     timed("extended_outgoing_ext32", lambda: (ex.step(rho, 1.0, dt, nsub), ex.accel()), (n + 2 * e) ** 3 * nsub)
     res["extended_outgoing_ext32"]["grid"] = n + 2 * e
     ex.close()
+    for ec in (16, 64):
+        ns = hgs.NestedSolver(n, ec, bc="robin", storage="f32", eta=0.0, device=dev)
+        timed(f"nested_robin_ext{ec}", lambda: (ns.step(rho, 1.0, dt, nsub), ns.accel(g)), n ** 3 * nsub)
+        res[f"nested_robin_ext{ec}"]["coarse_grid"] = n // 2 + 2 * ec
+        ns.close()
     gen = torch.Generator(device=dev)
     gen.manual_seed(5)
     cs = 0.05 + 0.05 * torch.rand((n, n, n), device=dev, generator=gen)

@@ -240,6 +240,35 @@ hgs_status hgs_extract(const void* outer, int32_t nx, int32_t ny, int32_t nz, in
 hgs_status hgs_accel_box(hgs_ctx* ctx, int32_t i0, int32_t j0, int32_t k0, int32_t bx, int32_t by, int32_t bz,
                          void* gx, void* gy, void* gz);
 
+/* ---- Nested coarse outer level ----------------------------------------------
+ * Sec. 4 names nested grids as a way to put the outer boundary far from the
+ * matter at little cost; it gives no scheme, and the one here is this
+ * library's reading.  A coarse context of cell size 2 dx covers the fine grid
+ * and ext coarse cells more on every side (corner moved out by 2 ext dx),
+ * with a local boundary (ROBIN or OUTGOING) at its faces; the fine context has
+ * bc = USER.  Per hydrodynamical step: hgs_nest_source gives the coarse
+ * density, the coarse context takes ceil(nsub / 2) substeps spanning
+ * nsub * dt, hgs_nest_ghosts turns its potential (hgs_potential) into the
+ * fine ghosts for hgs_set_boundary, and the fine context takes its nsub
+ * substeps with those ghosts frozen.  Device buffers of the given dtype,
+ * enqueued on stream, no synchronisation.
+ * hgs_nest_source: coarse (nz/2 + 2 ext, ny/2 + 2 ext, nx/2 + 2 ext) = the
+ *   means of rho (nz, ny, nx) over 2 x 2 x 2 blocks in the centre, 0 in the
+ *   extension (every coarse cell written).  HGS_ERR_ARG for NULL pointers,
+ *   odd or out-of-range sizes, ext < 0 or a bad dtype.
+ * hgs_nest_ghosts: faces (the layout of hgs_set_boundary for an (nz, ny, nx)
+ *   grid with lower corner fine_x0[3] (host) and cell fine_dx) = the coarse
+ *   compact potential (mz, my, mx; corner coarse_x0[3], cell coarse_dx)
+ *   interpolated trilinearly between the nearest coarse cell centres at every
+ *   ghost centre, in FP64.  HGS_ERR_ARG for NULL pointers, sizes out of range
+ *   (coarse at least 2 per axis), cell sizes not positive and finite, or a
+ *   ghost centre outside the span of the coarse cell centres. */
+hgs_status hgs_nest_source(const void* rho, int32_t nx, int32_t ny, int32_t nz, int32_t ext, void* coarse,
+                           int32_t dtype, void* stream);
+hgs_status hgs_nest_ghosts(const void* coarse_phi, int32_t mx, int32_t my, int32_t mz, const double* coarse_x0,
+                           double coarse_dx, int32_t nx, int32_t ny, int32_t nz, const double* fine_x0,
+                           double fine_dx, void* faces, int32_t dtype, void* stream);
+
 /* Bitwise copy of the raw two-level state (phi^n, phi^{n-1} interiors, device
  * (nz,ny,nx) buffers) and the previous step size, for checkpoint/resume. */
 hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev);

@@ -22,6 +22,7 @@
 #include "k_tblock.hpp"
 #include "k_batch.hpp"
 #include "k_local.hpp"
+#include "k_nest.hpp"
 #include <algorithm>
 #include <cstdlib>
 #include <fstream>
@@ -987,6 +988,68 @@ hgs_status hgs_extract(const void* outer, int32_t nx, int32_t ny, int32_t nz, in
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? HGS_OK
                            : fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_extract: ") + hipGetErrorString(e));
+}
+
+hgs_status hgs_nest_source(const void* rho, int32_t nx, int32_t ny, int32_t nz, int32_t ext, void* coarse,
+                           int32_t dtype, void* stream) {
+    if (!rho || !coarse) return fail(nullptr, HGS_ERR_ARG, "rho and coarse must be non-NULL");
+    if (nx < 2 || ny < 2 || nz < 2 || nx % 2 || ny % 2 || nz % 2 || nx > kMaxN || ny > kMaxN || nz > kMaxN)
+        return fail(nullptr, HGS_ERR_ARG, "need even nx, ny, nz in 2..8192");
+    if (ext < 0 || ext > kMaxN || nx / 2 + 2 * (int64_t)ext > kMaxN || ny / 2 + 2 * (int64_t)ext > kMaxN ||
+        nz / 2 + 2 * (int64_t)ext > kMaxN)
+        return fail(nullptr, HGS_ERR_ARG, "need ext >= 0 and a coarse grid of at most 8192 cells along an axis");
+    if (dtype != HGS_F32 && dtype != HGS_F64) return fail(nullptr, HGS_ERR_ARG, "dtype must be HGS_F32 or HGS_F64");
+    (void)hipGetLastError();
+    // one wave per coarse row, four rows per workgroup
+    const dim3 grid((ny / 2 + 2 * ext + 3) / 4, nz / 2 + 2 * ext);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == HGS_F32)
+        hipLaunchKernelGGL(k_nest_source<float>, grid, dim3(64, 4), 0, st, static_cast<const float*>(rho), nx, ny, nz,
+                           ext, static_cast<float*>(coarse));
+    else
+        hipLaunchKernelGGL(k_nest_source<double>, grid, dim3(64, 4), 0, st, static_cast<const double*>(rho), nx, ny,
+                           nz, ext, static_cast<double*>(coarse));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HGS_OK
+                           : fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_nest_source: ") + hipGetErrorString(e));
+}
+
+hgs_status hgs_nest_ghosts(const void* coarse_phi, int32_t mx, int32_t my, int32_t mz, const double* coarse_x0,
+                           double coarse_dx, int32_t nx, int32_t ny, int32_t nz, const double* fine_x0,
+                           double fine_dx, void* faces, int32_t dtype, void* stream) {
+    if (!coarse_phi || !coarse_x0 || !fine_x0 || !faces)
+        return fail(nullptr, HGS_ERR_ARG, "coarse_phi, coarse_x0, fine_x0 and faces must be non-NULL");
+    if (mx < 2 || my < 2 || mz < 2 || mx > kMaxN || my > kMaxN || mz > kMaxN || nx < 1 || ny < 1 || nz < 1 ||
+        nx > kMaxN || ny > kMaxN || nz > kMaxN)
+        return fail(nullptr, HGS_ERR_ARG, "need coarse sizes in 2..8192 and fine sizes in 1..8192");
+    if (!(coarse_dx > 0.0) || !std::isfinite(coarse_dx) || !(fine_dx > 0.0) || !std::isfinite(fine_dx))
+        return fail(nullptr, HGS_ERR_ARG, "cell sizes must be positive and finite");
+    if (dtype != HGS_F32 && dtype != HGS_F64) return fail(nullptr, HGS_ERR_ARG, "dtype must be HGS_F32 or HGS_F64");
+    const int m[3] = {mx, my, mz}, n[3] = {nx, ny, nz};
+    for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(coarse_x0[d]) || !std::isfinite(fine_x0[d]))
+            return fail(nullptr, HGS_ERR_ARG, "corners must be finite");
+        // the outermost ghost centres against the outermost coarse centres
+        const double lo = fine_x0[d] - 0.5 * fine_dx, hi = fine_x0[d] + (n[d] + 0.5) * fine_dx;
+        const double clo = coarse_x0[d] + 0.5 * coarse_dx, chi = coarse_x0[d] + (m[d] - 0.5) * coarse_dx;
+        const double tol = 1e-9 * coarse_dx;
+        if (lo < clo - tol || hi > chi + tol)
+            return fail(nullptr, HGS_ERR_ARG, "the fine ghost centres must lie within the span of the coarse centres");
+    }
+    (void)hipGetLastError();
+    const NestGeom g{mx, my, mz, coarse_x0[0], coarse_x0[1], coarse_x0[2], coarse_dx,
+                     nx, ny, nz, fine_x0[0],   fine_x0[1],   fine_x0[2],   fine_dx};
+    const dim3 grid((std::max(nx, ny) + 255) / 256, std::max(ny, nz), 6);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (dtype == HGS_F32)
+        hipLaunchKernelGGL(k_nest_ghosts<float>, grid, dim3(256), 0, st, static_cast<const float*>(coarse_phi), g,
+                           static_cast<float*>(faces));
+    else
+        hipLaunchKernelGGL(k_nest_ghosts<double>, grid, dim3(256), 0, st, static_cast<const double*>(coarse_phi), g,
+                           static_cast<double*>(faces));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HGS_OK
+                           : fail(nullptr, HGS_ERR_DEVICE, std::string("hgs_nest_ghosts: ") + hipGetErrorString(e));
 }
 
 hgs_status hgs_save_raw(hgs_ctx* ctx, void* phi_n, void* phi_nm1, double* dt_prev) {

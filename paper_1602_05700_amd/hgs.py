@@ -71,6 +71,8 @@ _SIGS = {
     "hgs_energy": (_i32, [_vp, _vp, _dp]),
     "hgs_embed": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
     "hgs_extract": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
+    "hgs_nest_source": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
+    "hgs_nest_ghosts": (_i32, [_vp, _i32, _i32, _i32, _dp, _dbl, _i32, _i32, _i32, _dp, _dbl, _vp, _i32, _vp]),
     "hgs_save_raw": (_i32, [_vp, _vp, _vp, _dp]),
     "hgs_load_raw": (_i32, [_vp, _vp, _vp, _dbl]),
     "hgs_set_tblock": (_i32, [_vp, _i32]),
@@ -416,6 +418,76 @@ class ExtendedSolver:
 
     def close(self) -> None:
         self.solver.close()
+
+
+class NestedSolver:
+    """A fine grid whose outer boundary comes from a coarse outer level (Sec. 4
+    names nested grids as a way to move the boundary out cheaply): a coarse
+    grid of cell size 2 dx covering the fine one and `ext` coarse cells more
+    on every side, with a local boundary (Robin or outgoing) at its faces.
+    Per hydrodynamical step: the coarse density (hgs_nest_source), ceil(nsub/2)
+    coarse substeps spanning nsub * dt, the fine ghosts interpolated from the
+    coarse potential (hgs_nest_ghosts) and frozen, nsub fine substeps.  rho, phi
+    and g live on the fine grid (nz, ny, nx), all sizes even."""
+
+    def __init__(self, shape, ext: int, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, bc: str = "robin",
+                 storage: str = "f32", eta: float = 0.0, G: float = 1.0, origin=(0.0, 0.0, 0.0), tblock: int = 0,
+                 device="cuda", stream=None):
+        import torch
+
+        nz, ny, nx = (shape, shape, shape) if np.isscalar(shape) else shape
+        if bc not in ("robin", "outgoing"):
+            raise ValueError("the coarse level needs a local boundary: 'robin' or 'outgoing'")
+        if int(ext) < 1:
+            raise ValueError("ext must be at least 1")
+        dx = float(dx) if dx is not None else 2.0 / nx
+        self.ext = int(ext)
+        self.fine = Solver((nz, ny, nx), x0=x0, dx=dx, G=G, origin=origin, bc="user", storage=storage,
+                           tblock=tblock, eta=eta, device=device, stream=stream)
+        f = self.fine
+        h = 2.0 * dx
+        e = self.ext
+        self.coarse = Solver((nz // 2 + 2 * e, ny // 2 + 2 * e, nx // 2 + 2 * e),
+                             x0=tuple(float(v) - e * h for v in x0), dx=h, G=G, origin=origin, bc=bc,
+                             storage=storage, eta=eta, device=f.device, stream=f.stream)
+        self.shape, self.dtype, self.device, self.stream = f.shape, f.dtype, f.device, f.stream
+        self._code = HGS_F32 if f.dtype == torch.float32 else HGS_F64
+        self._rho_c = torch.empty(self.coarse.shape, dtype=f.dtype, device=f.device)
+        self._faces = torch.empty(f.face_count, dtype=f.dtype, device=f.device)
+        self._x0c = (ctypes.c_double * 3)(self.coarse.cfg.x0, self.coarse.cfg.y0, self.coarse.cfg.z0)
+        self._x0f = (ctypes.c_double * 3)(f.cfg.x0, f.cfg.y0, f.cfg.z0)
+
+    def coarse_source(self, rho):
+        nz, ny, nx = self.shape
+        _check(_lib.hgs_nest_source(self.fine._need(rho).data_ptr(), nx, ny, nz, self.ext, self._rho_c.data_ptr(),
+                                    self._code, self.stream.cuda_stream))
+        return self._rho_c
+
+    def fine_ghosts(self, phi_c):
+        mz, my, mx = self.coarse.shape
+        nz, ny, nx = self.shape
+        self.coarse._need(phi_c)
+        _check(_lib.hgs_nest_ghosts(phi_c.data_ptr(), mx, my, mz, self._x0c, self.coarse.cfg.dx, nx, ny, nz,
+                                    self._x0f, self.fine.cfg.dx, self._faces.data_ptr(), self._code,
+                                    self.stream.cuda_stream))
+        return self._faces
+
+    def step(self, rho, c_g: float, dt: float, nsub: int) -> None:
+        nsub = int(nsub)
+        ncs = (nsub + 1) // 2
+        self.coarse.step(self.coarse_source(rho), c_g, nsub * float(dt) / ncs, ncs)
+        self.fine.set_boundary(self.fine_ghosts(self.coarse.potential(with_phidot=False)[0]))
+        self.fine.step(rho, c_g, dt, nsub)
+
+    def potential(self, with_phidot: bool = True):
+        return self.fine.potential(with_phidot)
+
+    def accel(self, out=None):
+        return self.fine.accel(out)
+
+    def close(self) -> None:
+        self.fine.close()
+        self.coarse.close()
 
 
 def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32", lmax: int = 4,

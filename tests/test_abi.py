@@ -168,6 +168,23 @@ def test_embed_extract_host_checks():
     assert L.hgs_accel_box(None, 0, 0, 0, 1, 1, 1, a, a, a) == hgs.HGS_ERR_ARG
 
 
+def test_nest_host_checks():
+    L = hgs.library()
+    a = ctypes.c_void_p(16)  # never dereferenced: every case below fails validation first
+    assert L.hgs_nest_source(None, 8, 8, 8, 2, a, hgs.HGS_F32, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_nest_source(a, 8, 7, 8, 2, a, hgs.HGS_F32, None) == hgs.HGS_ERR_ARG  # odd size
+    assert L.hgs_nest_source(a, 8, 8, 8, -1, a, hgs.HGS_F32, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_nest_source(a, 8, 8, 8, 2, a, 5, None) == hgs.HGS_ERR_ARG
+    c0 = (ctypes.c_double * 3)(-1.5, -1.5, -1.5)  # coarse 6^3 at 0.5 around a fine 4^3 at 0.25
+    f0 = (ctypes.c_double * 3)(-0.5, -0.5, -0.5)
+    assert L.hgs_nest_ghosts(None, 6, 6, 6, c0, 0.5, 4, 4, 4, f0, 0.25, a, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_nest_ghosts(a, 1, 6, 6, c0, 0.5, 4, 4, 4, f0, 0.25, a, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_nest_ghosts(a, 6, 6, 6, c0, 0.0, 4, 4, 4, f0, 0.25, a, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
+    far = (ctypes.c_double * 3)(-0.5, -0.5, 0.6)  # ghost centres beyond the last coarse centre along z
+    assert L.hgs_nest_ghosts(a, 6, 6, 6, c0, 0.5, 4, 4, 4, far, 0.25, a, hgs.HGS_F64, None) == hgs.HGS_ERR_ARG
+    assert b"span" in L.hgs_last_error(None)
+
+
 def test_warmstart_criterion_checks():
     """Convergence criteria are checked before any solver is built."""
     from paper_1602_05700_amd import warmstart as ws

@@ -1,0 +1,65 @@
+"""The nested coarse outer level on the GPU (Sec. 4 names nested grids as a way
+to move the outer boundary out): the coarse source and the interpolated fine
+ghosts against the oracle's, and the two-level step against the oracle's
+NestedOracle over several hydro steps (odd and even substep counts), for the
+Robin and outgoing rules at the coarse faces."""
+import numpy as np
+import pytest
+
+from oracle.core import Grid
+from oracle.nested import NestedOracle, coarse_grid, coarse_source, fine_ghosts
+from test_gpu_parity import F32_TOL, F64_TOL, corner, dens, grid_of, host, npdt, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("shape,ext", [((8, 6, 10), 0), ((8, 6, 10), 3), ((2, 130, 4), 1), ((64, 64, 64), 8)])
+def test_nest_source_matches_oracle(gpu_lib, storage, shape, ext):
+    import torch
+
+    rho = np.random.default_rng(51).uniform(0.0, 2.0, shape).astype(npdt(storage))
+    nz, ny, nx = shape
+    out = torch.full((nz // 2 + 2 * ext, ny // 2 + 2 * ext, nx // 2 + 2 * ext), float("nan"),
+                     dtype=torch.float64 if storage == "f64" else torch.float32, device="cuda")
+    code = gpu_lib.HGS_F64 if storage == "f64" else gpu_lib.HGS_F32
+    L = gpu_lib.library()
+    r = to_dev(rho)
+    assert L.hgs_nest_source(r.data_ptr(), nx, ny, nz, ext, out.data_ptr(), code, None) == gpu_lib.HGS_OK
+    want = coarse_source(rho.astype(np.float64), ext)
+    tol = 1e-15 if storage == "f64" else 1e-7
+    assert rel(host(out), want) <= tol
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("shape,ext", [((12, 10, 14), 1), ((12, 10, 14), 3), ((6, 40, 300), 2)])
+def test_nest_ghosts_match_oracle(gpu_lib, storage, shape, ext):
+    g = grid_of(shape)
+    gc = coarse_grid(g, ext)
+    phi_c = np.random.default_rng(52).normal(size=gc.shape).astype(npdt(storage))
+    s = gpu_lib.NestedSolver(shape, ext, x0=corner(shape), dx=g.dx, storage=storage)
+    got = host(s.fine_ghosts(to_dev(phi_c)))
+    want = gpu_lib.faces_to_flat(fine_ghosts(g, phi_c.astype(np.float64), gc))
+    tol = 1e-14 if storage == "f64" else 1e-7
+    assert rel(got, want) <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["robin", "outgoing"])
+def test_nested_solver_matches_oracle(gpu_lib, storage, bc):
+    shape, ext = (12, 10, 14), 3
+    g = grid_of(shape)
+    rho = dens(shape, 53, storage)
+    s = gpu_lib.NestedSolver(shape, ext, x0=corner(shape), dx=g.dx, bc=bc, storage=storage, eta=1.5)
+    o = NestedOracle(g, ext, bc=bc, eta=1.5)
+    dt = 0.4 * g.dx
+    for nsub in (4, 5, 4, 8):
+        s.step(to_dev(rho), 1.0, dt, nsub)
+        o.step(rho.astype(np.float64), 1.0, dt, nsub)
+    tol = F64_TOL if storage == "f64" else F32_TOL
+    phi, _ = s.potential()
+    assert rel(host(phi), o.potential()[0]) < tol
+    for a, b in zip(s.accel(), o.accel()):
+        assert rel(host(a), b) < 10 * tol
+    s.close()
