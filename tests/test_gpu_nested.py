@@ -63,3 +63,38 @@ def test_nested_solver_matches_oracle(gpu_lib, storage, bc):
     for a, b in zip(s.accel(), o.accel()):
         assert rel(host(a), b) < 10 * tol
     s.close()
+
+
+def test_nested_full_size_256_f32(gpu_lib):
+    """The benchmarked nested configuration: 256^3 FP32 fine grid, the 8-blob
+    density, Robin 16 coarse cells beyond it (160^3 coarse), 4 substeps per
+    hydro step at the default fused depth, from a smooth non-zero start on
+    both levels, two hydro steps against the FP64 oracle over every cell."""
+    import torch
+
+    import workloads
+
+    n, ext = 256, 16
+    g = Grid.cube(n)
+    rho = workloads.blob_density_torch(n, workloads.blob_params(0, 8), "cuda", torch.float32)
+    s = gpu_lib.NestedSolver(n, ext, bc="robin", storage="f32", eta=0.0)
+    o = NestedOracle(g, ext, bc="robin", eta=0.0)
+    dt = 0.4 * g.dx
+
+    def smooth(grid):
+        x, y, z = (c[1:-1] for c in grid.centres())
+        r2 = z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2
+        return -1.0 / np.sqrt(r2 + 0.09)
+
+    for lev, olev, h in ((s.fine, o.fine, dt), (s.coarse, o.coarse, 2.0 * dt)):  # the coarse step is 2 dt
+        p0 = smooth(olev.g).astype(np.float32)
+        lev.set_state(to_dev(p0), None, h)
+        olev.set_state(p0.astype(np.float64), None, h)
+    r64 = host(rho)
+    for _ in range(2):
+        s.step(rho, 1.0, dt, 4)
+        o.step(r64, 1.0, dt, 4)
+    assert rel(host(s.potential()[0]), o.potential()[0]) < F32_TOL
+    for a, b in zip(s.accel(), o.accel()):
+        assert rel(host(a), b) < 10 * F32_TOL
+    s.close()
