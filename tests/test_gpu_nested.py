@@ -98,3 +98,24 @@ def test_nested_full_size_256_f32(gpu_lib):
     for a, b in zip(s.accel(), o.accel()):
         assert rel(host(a), b) < 10 * F32_TOL
     s.close()
+
+
+def test_nested_converges_to_composite_steady_state(gpu_lib):
+    """Damped, the two-level GPU step settles on the composite steady state
+    built from independent direct solves (a sparse Robin solve on the coarse
+    grid, a DST-I solve on the fine grid with the interpolated ghosts)."""
+    from test_oracle_nested import _composite_steady_state
+
+    shape, ext = (12, 10, 14), 3
+    g = grid_of(shape)
+    origin = (0.05, -0.03, 0.02)
+    rho = dens(shape, 54, "f64")
+    phi_ref, gc, A = _composite_steady_state(g, ext, rho, origin)
+    lam_min = float(np.linalg.eigvalsh(-A.toarray())[0])
+    s = gpu_lib.NestedSolver(shape, ext, x0=corner(shape), dx=g.dx, bc="robin", storage="f64",
+                             eta=2.0 * np.sqrt(lam_min), origin=origin)
+    r = to_dev(rho)
+    for _ in range(200):
+        s.step(r, 1.0, 0.4 * g.dx, 8)
+    assert rel(host(s.potential()[0]), phi_ref) < 1e-8
+    s.close()
