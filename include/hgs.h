@@ -7,10 +7,14 @@
  *     (-c_g^-2 d^2/dt^2 + Laplacian) phi = 4 pi G rho                (Eq. 2)
  * by explicit time stepping on the hydrodynamic grid.  Per hydrodynamical step
  * the density is frozen and the wave equation is sub-cycled with a smaller step
- * (Sec. 2, separate timelines for gravity and hydrodynamics); the outer
- * boundary is either a Dirichlet condition from a multipole expansion of rho
- * (Sec. 2 and Sec. 4, Table I model aD05) or a caller-supplied one; the
- * gravitational acceleration is g = -grad phi.
+ * (Sec. 2, separate timelines for gravity and hydrodynamics).  The outer
+ * boundary is a Dirichlet condition from a multipole expansion of rho (Sec. 2
+ * and Sec. 4, Table I model aD05), a caller-supplied Dirichlet one, or a local
+ * one that follows the interior every substep (Robin -- the paper's default --,
+ * its outgoing-wave form, periodic; Sec. 2 and Sec. 4).  Calls near the end
+ * move a local boundary away from the matter (Sec. 4): an extended
+ * gravity-only grid and a nested coarse outer level.  The gravitational
+ * acceleration is g = -grad phi.
  *
  * Discretisation (Sec. 2 leaves it unspecified):
  *   cell-centred uniform grid of nx*ny*nz cubic cells of size dx; cell (i,j,k)
