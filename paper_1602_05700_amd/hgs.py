@@ -440,6 +440,8 @@ class NestedSolver:
             raise ValueError("the coarse level needs a local boundary: 'robin' or 'outgoing'")
         if int(ext) < 1:
             raise ValueError("ext must be at least 1")
+        if nx % 2 or ny % 2 or nz % 2:
+            raise ValueError("the fine grid needs even sizes (2 x 2 x 2 cells per coarse cell)")
         dx = float(dx) if dx is not None else 2.0 / nx
         self.ext = int(ext)
         self.fine = Solver((nz, ny, nx), x0=x0, dx=dx, G=G, origin=origin, bc="user", storage=storage,
