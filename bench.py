@@ -157,9 +157,18 @@ def run_batched(dev, nsub=500, seed=2, count=64):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     cells = sum(n ** 3 for n in spec.sizes)
+    T = b.grids[0].tblock
+    # algorithmic bytes of the substeps: per fused launch each cell's phi^n,
+    # phi^{n-1} and rho are read and two levels written (FP32), per streaming
+    # substep three reads and one write; the moments and ghosts once per step
+    # are counted in the time but not in the bytes
+    launches = nsub // T if T > 1 else nsub
+    stencil_bytes = (20.0 if T > 1 else 16.0) * cells * launches + 16.0 * cells * (nsub - launches * max(T, 1))
+    gbps = stencil_bytes / (ms / 1e3) / 1e9
     return {"grids": count, "cells": cells, "substeps": nsub, "ms_per_hydro_step": round(ms, 3),
             "value": round(cells * nsub / (ms / 1e3) / 1e9, 3), "unit": "Gcell-updates/s",
-            "graph": b.used_graph, "tblock": b.grids[0].tblock}
+            "graph": b.used_graph, "tblock": T, "stencil_GBps_algorithmic": round(gbps, 1),
+            "hbm_frac": round(gbps / PEAK_HBM_GBS, 4)}
 
 
 def run_configs(dev):
