@@ -316,6 +316,88 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
     return res
 
 
+def run_domain_study(dev, n=128):
+    """Sec. 4 / Table I style: error of the converged potential against the
+    closed-form free-space one, for the outer boundary at the hydro faces
+    (Robin), pushed out by an extended gravity-only grid or by a nested coarse
+    level, and for the multipole Dirichlet boundary.  Two Gaussians off the
+    expansion centre on n^3 over [-1, 1]^3, FP64 storage, each run damped
+    (eta for the slowest mode of its outermost grid) for 60 e-folds of that
+    mode.  Reported per run: the paper's average relative error (Eq. 6) and
+    the largest relative error over the hydro region, R_b of the final state,
+    the substeps and the GPU time."""
+    import math
+
+    import torch
+
+    from paper_1602_05700_amd import hgs
+
+    dx = 2.0 / n
+    dt = 0.4 * dx
+    ax = -1.0 + (torch.arange(n, device=dev, dtype=torch.float64) + 0.5) * dx
+    Z, Y, X = torch.meshgrid(ax, ax, ax, indexing="ij")
+    rho = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    exact = torch.zeros_like(rho)
+    for (cx, cy, cz), a0, sg in (((0.35, 0.1, 0.0), 1.0, 0.2), ((-0.3, -0.2, 0.15), 0.6, 0.16)):
+        r = torch.sqrt((X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2)
+        rho += a0 * torch.exp(-0.5 * r ** 2 / sg ** 2)
+        mass = a0 * (2.0 * math.pi) ** 1.5 * sg ** 3
+        exact += -mass * torch.erf(r / (math.sqrt(2.0) * sg)) / r
+    del X, Y, Z
+
+    def errors(phi):
+        d = (phi - exact) / exact
+        return float(torch.sqrt(torch.mean(d * d))), float(torch.max(torch.abs(d)))
+
+    def robin_eta(half):  # slowest Robin mode of a box of half-width `half`, critically damped
+        return 2.0 * math.sqrt(0.66) * math.pi / (2.0 * half)
+
+    out = {}
+
+    def record(label, run, potential, residual, substeps):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        eq6, mx = errors(potential())
+        out[label] = {"eq6": eq6, "max_rel": mx, "R_b": float(residual()[0]), "substeps": substeps,
+                      "ms": round(e0.elapsed_time(e1), 2)}
+
+    lam = 3.0 * (4.0 / dx ** 2) * math.sin(math.pi / (2 * (n + 1))) ** 2
+    eta = 2.0 * math.sqrt(lam)
+    steps = int(60.0 / (eta * dt))
+    sv = hgs.Solver(n, storage="f64", lmax=4, eta=eta, bc="multipole", device=dev)
+    record("multipole_dirichlet", lambda: sv.step(rho, 1.0, dt, steps), lambda: sv.potential(False)[0],
+           lambda: sv.residual(rho), steps)
+    sv.close()
+    for e in (0, 16, 32, 64):
+        eta = robin_eta(1.0 + e * dx)
+        steps = int(60.0 / (eta * dt))
+        ex = hgs.ExtendedSolver(n, e, bc="robin", storage="f64", eta=eta, device=dev)
+        record("robin_at_faces" if e == 0 else f"extended_e{e}", lambda: ex.step(rho, 1.0, dt, steps),
+               lambda: ex.potential(False)[0], lambda: ex.residual(rho), steps)
+        ex.close()
+    for ec in (8, 16, 32):
+        eta = robin_eta(1.0 + 2 * ec * dx)
+        calls = int(60.0 / (eta * dt)) // 8 + 1
+        ns = hgs.NestedSolver(n, ec, bc="robin", storage="f64", eta=eta, device=dev)
+
+        def run_nested():
+            for _ in range(calls):
+                ns.step(rho, 1.0, dt, 8)
+
+        record(f"nested_e{ec}", run_nested, lambda: ns.potential(False)[0], lambda: ns.fine.residual(rho),
+               calls * 8)
+        out[f"nested_e{ec}"]["coarse_R_b"] = float(ns.coarse.residual(ns.coarse_source(rho))[0])
+        ns.close()
+    return {"grid": n, "storage": "f64", "reference": "closed-form free-space potential of two Gaussians",
+            "boundary_half_width": {"robin_at_faces": 1.0, **{f"extended_e{e}": 1.0 + e * dx for e in (16, 32, 64)},
+                                    **{f"nested_e{ec}": 1.0 + 2 * ec * dx for ec in (8, 16, 32)}},
+            "runs": out}
+
+
 def run_warmstart(dev, count=8, n=128, tol=1e-4):
     """Substeps of the critically damped FP32 solver to R_b < tol on 128^3
     blob mixtures (held-out seeds 20000..), from the zero start and from the
@@ -407,6 +489,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched measurement")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the steps-to-1e-4 warm-start measurement")
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^3 sphere and 256^3 rotating-blob runs")
+    ap.add_argument("--no-study", action="store_true", help="skip the boundary-placement error study")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (for scaling HBM counters)")
     args = ap.parse_args()
@@ -572,6 +655,10 @@ def main():
         log("[bench] smaller configurations: 64^3 sphere (FP64), 256^3 rotating blobs (FP64, FP32)")
         line["configs"] = run_configs(dev)
         log(f"[bench]   {line['configs']}")
+    if not args.no_study:
+        log("[bench] boundary study at 128^3: converged error against the free-space potential")
+        line["domain_study"] = run_domain_study(dev)
+        log(f"[bench]   {line['domain_study']}")
     if not args.no_warmstart:
         log("[bench] warm start: steps to R_b < 1e-4 at 128^3, zero vs learned")
         line["warm_start"] = run_warmstart(dev)
