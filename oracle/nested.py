@@ -15,8 +15,10 @@ grids.  It gives no scheme for the latter; the reading taken here is:
   stay fixed over the fine substeps, as the multipole ghosts do;
 * the fine grid advances nsub substeps of dt.
 
-The fine and coarse grids share G, eta and the expansion centre ``origin``
-(the Robin relation's centre).
+More levels repeat this outwards: each level has twice the cell size of the
+one inside it and extends ``ext`` of its cells beyond it; only the outermost
+has the local boundary.  All levels share G, eta and the expansion centre
+``origin`` (the Robin relation's centre).
 """
 import numpy as np
 
@@ -73,22 +75,39 @@ def fine_ghosts(g: Grid, phi_c: np.ndarray, gc: Grid):
 
 
 class NestedOracle:
-    """Fine grid g (bc "user") with its ghosts from a coarse outer grid."""
+    """Fine grid g (bc "user") with its ghosts from coarser outer levels:
+    level 1 has cell size 2 dx and extends ext of its cells beyond g, level 2
+    the same around level 1, and so on up to ``levels - 1``; the outermost has
+    the local boundary ``bc``, every inner level bc "user".  A hydro step of
+    nsub substeps: the sources are restricted level by level, level l takes
+    ceil(n_{l-1} / 2) substeps spanning nsub * dt (n_0 = nsub), and the levels
+    are advanced from the outermost inwards, each inner one after its ghosts
+    are interpolated from the level around it."""
 
     def __init__(self, g: Grid, ext: int, bc: str = "robin", G: float = 1.0, eta: float = 0.0,
-                 origin=(0.0, 0.0, 0.0), storage: str = "f64"):
+                 origin=(0.0, 0.0, 0.0), storage: str = "f64", levels: int = 2):
         if ext < 1:
             raise ValueError("the coarse grid must extend at least one cell beyond the fine one")
+        if levels < 2:
+            raise ValueError("at least one coarse level")
         self.g, self.ext = g, ext
-        self.gc = coarse_grid(g, ext)
-        self.fine = Oracle(g, G=G, eta=eta, bc="user", origin=origin, storage=storage)
-        self.coarse = Oracle(self.gc, G=G, eta=eta, bc=bc, origin=origin, storage=storage)
+        self.grids = [g]
+        for _ in range(levels - 1):
+            self.grids.append(coarse_grid(self.grids[-1], ext))
+        self.levels = [Oracle(q, G=G, eta=eta, bc=(bc if i == levels - 1 else "user"), origin=origin,
+                              storage=storage) for i, q in enumerate(self.grids)]
+        self.fine, self.coarse, self.gc = self.levels[0], self.levels[1], self.grids[1]
 
     def step(self, rho: np.ndarray, c: float, dt: float, nsub: int) -> None:
-        ncs = (nsub + 1) // 2
-        self.coarse.step(coarse_source(rho, self.ext), c, nsub * dt / ncs, ncs)
-        self.fine.set_boundary(fine_ghosts(self.g, self.coarse.potential()[0], self.gc))
-        self.fine.step(rho, c, dt, nsub)
+        srcs, counts = [np.asarray(rho, dtype=np.float64)], [nsub]
+        for _ in range(1, len(self.levels)):
+            srcs.append(coarse_source(srcs[-1], self.ext))
+            counts.append((counts[-1] + 1) // 2)
+        for lev in range(len(self.levels) - 1, -1, -1):
+            if lev < len(self.levels) - 1:
+                outer = self.levels[lev + 1]
+                self.levels[lev].set_boundary(fine_ghosts(self.grids[lev], outer.potential()[0], self.grids[lev + 1]))
+            self.levels[lev].step(srcs[lev], c, dt if lev == 0 else nsub * dt / counts[lev], counts[lev])
 
     def potential(self):
         return self.fine.potential()

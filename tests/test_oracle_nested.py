@@ -76,6 +76,38 @@ def test_damped_nested_iteration_reaches_the_composite_steady_state():
     assert np.max(np.abs(phi - phi_ref)) < 1e-9 * np.max(np.abs(phi_ref))
 
 
+def test_three_levels_reach_their_composite_steady_state():
+    """Three levels (cell sizes dx, 2 dx, 4 dx): the damped iteration settles
+    on a sparse Robin solve of the outermost level, then DST-I solves of the
+    middle and fine levels, each with ghosts interpolated from the level
+    around it."""
+    g = Grid.cube(16)
+    origin = (0.0, 0.0, 0.0)
+    X, Y, Z = analytic.cell_centres(g)
+    rho = np.exp(-0.5 * ((X - 0.2) ** 2 + (Y + 0.1) ** 2 + Z ** 2) / 0.25 ** 2)
+    ext = 2
+    g1 = coarse_grid(g, ext)
+    g2 = coarse_grid(g1, ext)
+    r1 = coarse_source(rho, ext)
+    r2 = coarse_source(r1, ext)
+    A = _robin_matrix(g2, origin)
+    phi2 = spla.spsolve(A.tocsc(), 4.0 * np.pi * r2.ravel()).reshape(g2.shape)
+    P1 = padded(g1)
+    set_faces(P1, fine_ghosts(g1, phi2, g2))
+    phi1 = poisson.solve_dst(g1, r1, 1.0, P1)
+    P0 = padded(g)
+    set_faces(P0, fine_ghosts(g, phi1, g1))
+    phi_ref = poisson.solve_dst(g, rho, 1.0, P0)
+    lam_min = float(np.linalg.eigvalsh(-A.toarray())[0])
+    o = NestedOracle(g, ext, bc="robin", eta=2.0 * np.sqrt(lam_min), origin=origin, levels=3)
+    assert [q.nx for q in o.grids] == [16, 12, 10]
+    dt = 0.4 * g.dx
+    for _ in range(150):
+        o.step(rho, 1.0, dt, 8)
+    phi = o.potential()[0]
+    assert np.max(np.abs(phi - phi_ref)) < 1e-9 * np.max(np.abs(phi_ref))
+
+
 def test_outer_boundary_further_out_is_closer_to_free_space():
     """Sec. 4: the error of a local boundary falls as it moves away from the
     matter.  Two Gaussians off the expansion centre (so that the monopole
