@@ -254,9 +254,10 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
     (one substep per launch plus a ghost launch), the extended grid (32 vacuum
     cells on every side, outgoing boundary, rho embedded every hydro step, g on
     the hydrodynamics region; updates counted over the whole wider grid), the
-    nested coarse outer level (Robin at the coarse faces, 16 or 64 coarse
-    cells beyond the fine grid; coarse source, coarse substeps, interpolated
-    ghosts and the fine substeps at the fused depth; fine updates counted) and
+    nested coarse outer levels (Robin at the outermost faces; one level 16 or
+    64 coarse cells beyond the fine grid, or two levels of 16 cells each;
+    coarse sources, coarse substeps, interpolated ghosts and the fine substeps
+    at the fused depth; fine updates counted) and
     the hydro-coupled driver (signal-speed reduction over c_s and v, k_g = 5,
     Courant numbers 0.3: 5 substeps per hydro step).  Each entry: ms per
     hydro step (step + gradient) and cell updates per second."""
@@ -293,10 +294,11 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
     timed("extended_outgoing_ext32", lambda: (ex.step(rho, 1.0, dt, nsub), ex.accel()), (n + 2 * e) ** 3 * nsub)
     res["extended_outgoing_ext32"]["grid"] = n + 2 * e
     ex.close()
-    for ec in (16, 64):
-        ns = hgs.NestedSolver(n, ec, bc="robin", storage="f32", eta=0.0, device=dev)
-        timed(f"nested_robin_ext{ec}", lambda: (ns.step(rho, 1.0, dt, nsub), ns.accel(g)), n ** 3 * nsub)
-        res[f"nested_robin_ext{ec}"]["coarse_grid"] = n // 2 + 2 * ec
+    for ec, lv in ((16, 2), (64, 2), (16, 3)):
+        ns = hgs.NestedSolver(n, ec, bc="robin", storage="f32", eta=0.0, device=dev, levels=lv)
+        label = f"nested_robin_ext{ec}" if lv == 2 else f"nested{lv}_robin_ext{ec}"
+        timed(label, lambda: (ns.step(rho, 1.0, dt, nsub), ns.accel(g)), n ** 3 * nsub)
+        res[label]["coarse_grids"] = [t.shape[0] for t in ns.solvers[1:]]
         ns.close()
     gen = torch.Generator(device=dev)
     gen.manual_seed(5)
@@ -319,8 +321,8 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
 def run_domain_study(dev, n=128):
     """Sec. 4 / Table I style: error of the converged potential against the
     closed-form free-space one, for the outer boundary at the hydro faces
-    (Robin), pushed out by an extended gravity-only grid or by a nested coarse
-    level, and for the multipole Dirichlet boundary.  Two Gaussians off the
+    (Robin), pushed out by an extended gravity-only grid or by one to three
+    nested coarse levels, and for the multipole Dirichlet boundary.  Two Gaussians off the
     expansion centre on n^3 over [-1, 1]^3, FP64 storage, each run damped
     (eta for the slowest mode of its outermost grid) for 60 e-folds of that
     mode.  Reported per run: the paper's average relative error (Eq. 6) and
@@ -379,23 +381,23 @@ def run_domain_study(dev, n=128):
         record("robin_at_faces" if e == 0 else f"extended_e{e}", lambda: ex.step(rho, 1.0, dt, steps),
                lambda: ex.potential(False)[0], lambda: ex.residual(rho), steps)
         ex.close()
-    for ec in (8, 16, 32):
-        eta = robin_eta(1.0 + 2 * ec * dx)
+    half = {"robin_at_faces": 1.0, **{f"extended_e{e}": 1.0 + e * dx for e in (16, 32, 64)}}
+    for ec, lv in ((8, 2), (16, 2), (32, 2), (16, 3), (16, 4)):
+        hw = 1.0 + sum(ec * 2 ** (k + 1) * dx for k in range(lv - 1))  # half-width of the outermost level
+        label = f"nested_e{ec}" if lv == 2 else f"nested{lv}_e{ec}"
+        half[label] = hw
+        eta = robin_eta(hw)
         calls = int(60.0 / (eta * dt)) // 8 + 1
-        ns = hgs.NestedSolver(n, ec, bc="robin", storage="f64", eta=eta, device=dev)
+        ns = hgs.NestedSolver(n, ec, bc="robin", storage="f64", eta=eta, device=dev, levels=lv)
 
         def run_nested():
             for _ in range(calls):
                 ns.step(rho, 1.0, dt, 8)
 
-        record(f"nested_e{ec}", run_nested, lambda: ns.potential(False)[0], lambda: ns.fine.residual(rho),
-               calls * 8)
-        out[f"nested_e{ec}"]["coarse_R_b"] = float(ns.coarse.residual(ns.coarse_source(rho))[0])
+        record(label, run_nested, lambda: ns.potential(False)[0], lambda: ns.fine.residual(rho), calls * 8)
         ns.close()
     return {"grid": n, "storage": "f64", "reference": "closed-form free-space potential of two Gaussians",
-            "boundary_half_width": {"robin_at_faces": 1.0, **{f"extended_e{e}": 1.0 + e * dx for e in (16, 32, 64)},
-                                    **{f"nested_e{ec}": 1.0 + 2 * ec * dx for ec in (8, 16, 32)}},
-            "runs": out}
+            "boundary_half_width": half, "runs": out}
 
 
 def run_warmstart(dev, count=8, n=128, tol=1e-4):

@@ -421,18 +421,22 @@ class ExtendedSolver:
 
 
 class NestedSolver:
-    """A fine grid whose outer boundary comes from a coarse outer level (Sec. 4
-    names nested grids as a way to move the boundary out cheaply): a coarse
-    grid of cell size 2 dx covering the fine one and `ext` coarse cells more
-    on every side, with a local boundary (Robin or outgoing) at its faces.
-    Per hydrodynamical step: the coarse density (hgs_nest_source), ceil(nsub/2)
-    coarse substeps spanning nsub * dt, the fine ghosts interpolated from the
-    coarse potential (hgs_nest_ghosts) and frozen, nsub fine substeps.  rho, phi
-    and g live on the fine grid (nz, ny, nx), all sizes even."""
+    """A fine grid whose outer boundary comes from coarse outer levels (Sec. 4
+    names nested grids as a way to move the boundary out cheaply).  Level 1
+    has cell size 2 dx, covers the fine grid and `ext` of its cells more on
+    every side; each further level (up to `levels - 1`) does the same around
+    the one inside it.  The outermost level has a local boundary (Robin or
+    outgoing), every inner level frozen Dirichlet ghosts.  Per hydrodynamical
+    step: the densities restricted level by level (hgs_nest_source), then from
+    the outermost level inwards: level l takes ceil(n_{l-1} / 2) substeps
+    spanning nsub * dt (n_0 = nsub), and the level inside it gets its ghosts
+    interpolated from it (hgs_nest_ghosts) before its own substeps.  rho, phi
+    and g live on the fine grid (nz, ny, nx); every level but the outermost
+    needs even sizes."""
 
     def __init__(self, shape, ext: int, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, bc: str = "robin",
                  storage: str = "f32", eta: float = 0.0, G: float = 1.0, origin=(0.0, 0.0, 0.0), tblock: int = 0,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, levels: int = 2):
         import torch
 
         nz, ny, nx = (shape, shape, shape) if np.isscalar(shape) else shape
@@ -440,46 +444,67 @@ class NestedSolver:
             raise ValueError("the coarse level needs a local boundary: 'robin' or 'outgoing'")
         if int(ext) < 1:
             raise ValueError("ext must be at least 1")
-        if nx % 2 or ny % 2 or nz % 2:
-            raise ValueError("the fine grid needs even sizes (2 x 2 x 2 cells per coarse cell)")
+        if int(levels) < 2:
+            raise ValueError("levels must be at least 2 (the fine grid and one coarse level)")
+        self.ext = e = int(ext)
         dx = float(dx) if dx is not None else 2.0 / nx
-        self.ext = int(ext)
-        self.fine = Solver((nz, ny, nx), x0=x0, dx=dx, G=G, origin=origin, bc="user", storage=storage,
-                           tblock=tblock, eta=eta, device=device, stream=stream)
+        sizes, corners, cells = [(nz, ny, nx)], [tuple(float(v) for v in x0)], [dx]
+        for _ in range(int(levels) - 1):
+            if any(v % 2 for v in sizes[-1]):
+                raise ValueError(f"a level of shape {sizes[-1]} is not even: 2 x 2 x 2 cells per coarser cell")
+            h = 2.0 * cells[-1]
+            sizes.append(tuple(v // 2 + 2 * e for v in sizes[-1]))
+            corners.append(tuple(v - e * h for v in corners[-1]))
+            cells.append(h)
+        L = len(sizes)
+        self.solvers = []
+        for i in range(L):
+            outer = i == L - 1
+            kw = dict(x0=corners[i], dx=cells[i], G=G, origin=origin, bc=bc if outer else "user", storage=storage,
+                      eta=eta)
+            if i == 0:
+                s = Solver(sizes[0], tblock=tblock, device=device, stream=stream, **kw)
+            else:
+                s = Solver(sizes[i], device=self.solvers[0].device, stream=self.solvers[0].stream, **kw)
+            self.solvers.append(s)
+        self.fine, self.coarse = self.solvers[0], self.solvers[1]
         f = self.fine
-        h = 2.0 * dx
-        e = self.ext
-        self.coarse = Solver((nz // 2 + 2 * e, ny // 2 + 2 * e, nx // 2 + 2 * e),
-                             x0=tuple(float(v) - e * h for v in x0), dx=h, G=G, origin=origin, bc=bc,
-                             storage=storage, eta=eta, device=f.device, stream=f.stream)
         self.shape, self.dtype, self.device, self.stream = f.shape, f.dtype, f.device, f.stream
         self._code = HGS_F32 if f.dtype == torch.float32 else HGS_F64
-        self._rho_c = torch.empty(self.coarse.shape, dtype=f.dtype, device=f.device)
-        self._faces = torch.empty(f.face_count, dtype=f.dtype, device=f.device)
-        self._x0c = (ctypes.c_double * 3)(self.coarse.cfg.x0, self.coarse.cfg.y0, self.coarse.cfg.z0)
-        self._x0f = (ctypes.c_double * 3)(f.cfg.x0, f.cfg.y0, f.cfg.z0)
+        self._rho = [None] + [torch.empty(s.shape, dtype=f.dtype, device=f.device) for s in self.solvers[1:]]
+        self._faces = [torch.empty(s.face_count, dtype=f.dtype, device=f.device) for s in self.solvers[:-1]]
+        self._x0 = [(ctypes.c_double * 3)(s.cfg.x0, s.cfg.y0, s.cfg.z0) for s in self.solvers]
 
-    def coarse_source(self, rho):
-        nz, ny, nx = self.shape
-        _check(_lib.hgs_nest_source(self.fine._need(rho).data_ptr(), nx, ny, nz, self.ext, self._rho_c.data_ptr(),
-                                    self._code, self.stream.cuda_stream))
-        return self._rho_c
-
-    def fine_ghosts(self, phi_c):
-        mz, my, mx = self.coarse.shape
-        nz, ny, nx = self.shape
-        self.coarse._need(phi_c)
-        _check(_lib.hgs_nest_ghosts(phi_c.data_ptr(), mx, my, mz, self._x0c, self.coarse.cfg.dx, nx, ny, nz,
-                                    self._x0f, self.fine.cfg.dx, self._faces.data_ptr(), self._code,
+    def coarse_source(self, rho, level: int = 1):
+        """Density of `level` (>= 1) from the density of the level inside it."""
+        nz, ny, nx = self.solvers[level - 1].shape
+        self.solvers[level - 1]._need(rho)
+        _check(_lib.hgs_nest_source(rho.data_ptr(), nx, ny, nz, self.ext, self._rho[level].data_ptr(), self._code,
                                     self.stream.cuda_stream))
-        return self._faces
+        return self._rho[level]
+
+    def fine_ghosts(self, phi_c, level: int = 0):
+        """Ghost faces of `level` interpolated from the potential of level + 1."""
+        inner, outer = self.solvers[level], self.solvers[level + 1]
+        mz, my, mx = outer.shape
+        nz, ny, nx = inner.shape
+        outer._need(phi_c)
+        _check(_lib.hgs_nest_ghosts(phi_c.data_ptr(), mx, my, mz, self._x0[level + 1], outer.cfg.dx, nx, ny, nz,
+                                    self._x0[level], inner.cfg.dx, self._faces[level].data_ptr(), self._code,
+                                    self.stream.cuda_stream))
+        return self._faces[level]
 
     def step(self, rho, c_g: float, dt: float, nsub: int) -> None:
         nsub = int(nsub)
-        ncs = (nsub + 1) // 2
-        self.coarse.step(self.coarse_source(rho), c_g, nsub * float(dt) / ncs, ncs)
-        self.fine.set_boundary(self.fine_ghosts(self.coarse.potential(with_phidot=False)[0]))
-        self.fine.step(rho, c_g, dt, nsub)
+        srcs, counts = [rho], [nsub]
+        for lev in range(1, len(self.solvers)):
+            srcs.append(self.coarse_source(srcs[-1], lev))
+            counts.append((counts[-1] + 1) // 2)
+        for lev in range(len(self.solvers) - 1, -1, -1):
+            s = self.solvers[lev]
+            if lev < len(self.solvers) - 1:
+                s.set_boundary(self.fine_ghosts(self.solvers[lev + 1].potential(with_phidot=False)[0], lev))
+            s.step(srcs[lev], c_g, dt if lev == 0 else nsub * float(dt) / counts[lev], counts[lev])
 
     def potential(self, with_phidot: bool = True):
         return self.fine.potential(with_phidot)
@@ -488,8 +513,8 @@ class NestedSolver:
         return self.fine.accel(out)
 
     def close(self) -> None:
-        self.fine.close()
-        self.coarse.close()
+        for s in self.solvers:
+            s.close()
 
 
 def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32", lmax: int = 4,

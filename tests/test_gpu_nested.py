@@ -119,3 +119,25 @@ def test_nested_converges_to_composite_steady_state(gpu_lib):
         s.step(r, 1.0, 0.4 * g.dx, 8)
     assert rel(host(s.potential()[0]), phi_ref) < 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_three_levels_match_oracle(gpu_lib, storage):
+    """Three levels (dx, 2 dx, 4 dx), the outgoing rule at the outermost
+    faces, odd and even substep counts, against the oracle's three-level step."""
+    shape, ext = (16, 12, 20), 2
+    g = grid_of(shape)
+    rho = dens(shape, 55, storage)
+    s = gpu_lib.NestedSolver(shape, ext, x0=corner(shape), dx=g.dx, bc="outgoing", storage=storage, eta=1.0,
+                             levels=3)
+    o = NestedOracle(g, ext, bc="outgoing", eta=1.0, levels=3)
+    assert [t.shape for t in s.solvers] == [q.shape for q in o.grids]
+    dt = 0.4 * g.dx
+    for nsub in (4, 5, 8, 3):
+        s.step(to_dev(rho), 1.0, dt, nsub)
+        o.step(rho.astype(np.float64), 1.0, dt, nsub)
+    tol = F64_TOL if storage == "f64" else F32_TOL
+    assert rel(host(s.potential()[0]), o.potential()[0]) < tol
+    for a, b in zip(s.accel(), o.accel()):
+        assert rel(host(a), b) < 10 * tol
+    s.close()
