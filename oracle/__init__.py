@@ -54,8 +54,8 @@ arXiv:1602.05700), and what pins it (tests/test_oracle_pins.py):
   fine ghost centres.  Pinned by (tests/test_oracle_nested.py): exactness of
   the interpolation on affine fields, mass conservation of the source, the
   damped iteration reaching the composite steady state of a sparse Robin solve
-  and a DST-I solve, and the error against the free-space potential falling
-  as the coarse level extends further.
+  and DST-I solves (two and three levels), and the error against the
+  free-space potential falling as the coarse level extends further.
 
 Parity unpinned: none of the paper's own numerical results can be compared,
 because the paper prints no worked example, table of potentials or figure data
