@@ -254,8 +254,10 @@ hgs_status hgs_accel_box(hgs_ctx* ctx, int32_t i0, int32_t j0, int32_t k0, int32
  * density, the coarse context takes ceil(nsub / 2) substeps spanning
  * nsub * dt, hgs_nest_ghosts turns its potential (hgs_potential) into the
  * fine ghosts for hgs_set_boundary, and the fine context takes its nsub
- * substeps with those ghosts frozen.  Device buffers of the given dtype,
- * enqueued on stream, no synchronisation.
+ * substeps with those ghosts frozen.  More levels repeat this outwards (each
+ * inner one bc = USER, only the outermost local), advanced from the outermost
+ * inwards.  Device buffers of the given dtype, enqueued on stream, no
+ * synchronisation.
  * hgs_nest_source: coarse (nz/2 + 2 ext, ny/2 + 2 ext, nx/2 + 2 ext) = the
  *   means of rho (nz, ny, nx) over 2 x 2 x 2 blocks in the centre, 0 in the
  *   extension (every coarse cell written).  HGS_ERR_ARG for NULL pointers,
