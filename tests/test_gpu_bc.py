@@ -148,3 +148,35 @@ def test_local_bc_rejected_in_batch_and_tuned_to_one(gpu_lib):
     best, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc="periodic",
                                device="cuda")
     assert best == 1
+
+
+def test_periodic_and_energy_256_against_oracle(gpu_lib):
+    """At 256^3 (FP32, the size of the bench's next-row runs) the reductions
+    take their 16-byte, unrolled paths: the periodic mean of rho inside one
+    hydro step, and the energy sum W = 1/2 sum rho phi dx^3 of the result,
+    against the FP64 oracle."""
+    import torch
+
+    import workloads
+    from oracle.core import Grid
+
+    n = 256
+    g = Grid.cube(n)
+    rho = workloads.blob_density_torch(n, workloads.blob_params(0, 8), "cuda", torch.float32)
+    r64 = rho.double().cpu().numpy()
+    ax = -1.0 + (np.arange(n) + 0.5) * g.dx
+    p0 = (np.cos(np.pi * ax)[:, None, None] * np.sin(np.pi * ax)[None, :, None] * np.cos(np.pi * ax)[None, None, :])
+    s = gpu_lib.Solver(n, storage="f32", eta=0.5, bc="periodic")
+    o = Oracle(g, eta=0.5, bc="periodic")
+    dt = 0.4 * g.dx
+    s.set_state(torch.from_numpy(p0.astype(np.float32)).cuda(), None, dt)
+    o.set_state(p0.astype(np.float32).astype(np.float64), None, dt)
+    s.step(rho, 1.0, dt, 4)
+    o.step(r64, 1.0, dt, 4)
+    phi = s.potential(with_phidot=False)[0].double().cpu().numpy()
+    ref = o.potential()[0]
+    assert np.max(np.abs(phi - ref)) / np.max(np.abs(ref)) < 1e-4
+    # the energy of the GPU's own potential, on the scale of its terms
+    w = s.energy(rho)
+    terms = 0.5 * r64 * phi * g.dx ** 3
+    assert abs(w - terms.sum()) <= 1e-12 * np.abs(terms).sum()
