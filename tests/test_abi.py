@@ -193,3 +193,15 @@ def test_warmstart_criterion_checks():
         ws.steps_to_tolerance(None, 16, 1e-4, metric="R_x")
     with pytest.raises(ValueError):
         ws.steps_to_tolerance(None, 16, 1e-4, metric="E")  # E needs the converged reference
+
+
+def test_no_fallback_without_the_library(tmp_path):
+    """Without libhgs.so the binding refuses to import: there is no CPU path."""
+    import subprocess
+    import sys
+
+    env = dict(os.environ, HGS_LIBRARY=str(tmp_path / "absent" / "libhgs.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_1602_05700_amd.hgs"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libhgs.so" in r.stderr
