@@ -57,8 +57,15 @@ arXiv:1602.05700), and what pins it (tests/test_oracle_pins.py):
   and DST-I solves (two and three levels), and the error against the
   free-space potential falling as the coarse level extends further.
 
-Parity unpinned: none of the paper's own numerical results can be compared,
-because the paper prints no worked example, table of potentials or figure data
-(all figures are placeholders in the source text).
+The boundary study of Sec. 4 (Table I, kept as tests/golden/table1_models.txt)
+pins the outer boundaries together: at the table's domain ratios around one
+hydro grid the Robin boundary's error falls as the domain widens, and the
+multipole Dirichlet boundary on the hydro grid lies between the smallest and
+the widest Robin domain, the order the paper reports
+(tests/test_oracle_table1.py).
+
+Parity unpinned: no potential value of the paper's can be compared, because
+the paper prints no worked example, table of potentials or figure data (all
+figures are placeholders in the source text).
 """
 from .core import Grid, Oracle, lib  # noqa: F401
