@@ -3,7 +3,8 @@
 One step = one hydrodynamical step of the method: multipole moments of rho and
 the Dirichlet ghost shell, `nsub` leapfrog substeps of Eq. (2) with rho frozen,
 and the acceleration g = -grad phi.  Workload: 512^3 cell-centred grid on
-[-1, 1]^3, FP32 storage with FP64 arithmetic, rho a mixture of 16 Gaussian
+[-1, 1]^3, FP32 storage with the substeps in the FP32 increment form (moments,
+ghosts, gradient and norms in FP64), rho a mixture of 16 Gaussian
 blobs (seed 1) rigidly rotating about z at 0.1 c_g, multipole degree 4,
 4 substeps per hydro step, dt = 0.4 dx / c_g.  Every hydro step gets its own
 rotated density, generated into HBM before the timed region.

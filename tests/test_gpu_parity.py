@@ -126,18 +126,30 @@ def test_moments_match_legendre_brute_force(gpu_lib):
 
 # ------------------------------------------------------------------ leapfrog + gradient
 
+def rel_phidot(pd, rpd, rp, dt):
+    """Error of phidot = (phi^n - phi^{n-1}) / dt, the backward difference of
+    the two stored levels.  A relative error eps in those levels gives an error
+    up to 2 eps max|phi| / dt in phidot, which near a converged state (phidot
+    -> 0, rounding noise) exceeds phidot itself; so the error is measured
+    against the larger of max|phidot| and max|phi| / dt (the reading of
+    phidot's parity scale)."""
+    pd = np.asarray(pd, dtype=np.float64)
+    rpd = np.asarray(rpd, dtype=np.float64)
+    den = max(float(np.max(np.abs(rpd))), float(np.max(np.abs(rp))) / dt)
+    return float(np.max(np.abs(pd - rpd))) / (den if den > 0 else 1.0)
+
+
 def compare_state(s, o, storage, tol):
+    """phi, phidot and the vector field g against the oracle, each at the
+    stated bar (1e-10 FP64 storage, 1e-4 FP32 storage)."""
     phi, pd = s.potential()
     rp, rpd = o.potential()
     e_phi = rel(host(phi), rp)
-    # phidot = (phi^n - phi^{n-1})/dt: an eps-relative error in phi shows up as
-    # eps |phi| / dt, so near a converged state (phidot ~ rounding noise) its
-    # error is measured on that scale
-    e_pd = min(rel(host(pd), rpd), float(np.max(np.abs(host(pd) - rpd))) * o.dt_prev / np.max(np.abs(rp)))
+    e_pd = rel_phidot(host(pd), rpd, rp, o.dt_prev)
     gx, gy, gz = s.accel()
     ro = o.accel()
     e_g = rel_vec([host(a) for a in (gx, gy, gz)], ro)
-    assert e_phi < tol and e_pd < tol * 10 and e_g < tol * 10, (e_phi, e_pd, e_g)
+    assert e_phi < tol and e_pd < tol and e_g < tol, (e_phi, e_pd, e_g)
     return e_phi, e_pd, e_g
 
 
@@ -412,9 +424,8 @@ def test_full_size_512_f32_two_hydro_steps(gpu_lib):
         o.step(r64, 1.0, dt, 4)
     rp, rpd = o.potential()
     assert rel(host(phi), rp) < F32_TOL
-    assert rel(host(pd), rpd) < 10 * F32_TOL
-    for a, b in zip((gx, gy, gz), o.accel()):
-        assert rel(host(a), b) < 10 * F32_TOL
+    assert rel_phidot(host(pd), rpd, rp, dt) < F32_TOL
+    assert rel_vec([host(a) for a in (gx, gy, gz)], o.accel()) < F32_TOL
 
 
 @pytest.mark.slow
@@ -450,9 +461,8 @@ def test_config_256_rotating_blobs(gpu_lib, storage):
     phi, pd = s.potential()
     rp, rpd = o.potential()
     assert rel(host(phi), rp) < tol
-    assert rel(host(pd), rpd) < 10 * tol
-    for a, b in zip(s.accel(), o.accel()):
-        assert rel(host(a), b) < 10 * tol
+    assert rel_phidot(host(pd), rpd, rp, dt) < tol
+    assert rel_vec([host(a) for a in s.accel()], o.accel()) < tol
 
 
 # ------------------------------------------------------------------ temporal blocking
