@@ -391,6 +391,20 @@ hgs_status hgs_nn_lapmse(const float* out, const float* target, int32_t B, int32
  *   output y ([B][nvox][16]); inv_out_scale = 1 / out_scale. */
 #define HGS_NN_MAXABS_CHUNKS 64
 hgs_status hgs_nn_maxabs(const float* x, int32_t B, int64_t nvox, float* out, float* scratch, void* stream);
+/* hgs_nn_maxabs for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result, with the per-chunk partials in a static device
+ * array of the library (B * HGS_NN_MAXABS_CHUNKS floats, at most
+ * HGS_NN_MAXABS_NOALLOC_MAX_B samples: 1 MiB per device, held until the
+ * process ends) instead of a caller's scratch buffer.  Allocates nothing.
+ * The stream must belong to the current device.  Every call on one device
+ * shares that device's array: calls that overlap on one device (different
+ * streams or host threads without ordering) race and give undefined results.
+ * Errors: HGS_ERR_ARG for NULL pointers, nvox < 1 or B outside
+ * 1..HGS_NN_MAXABS_NOALLOC_MAX_B; HGS_ERR_DEVICE when the array's address
+ * cannot be obtained or a launch fails. */
+#define HGS_NN_MAXABS_NOALLOC_MAX_B 4096
+hgs_status hgs_nn_maxabs_noalloc(const float* x, int32_t B, int64_t nvox, float* out, void* stream);
 hgs_status hgs_nn_features(const float* rho, const float* phi, const float* scale, int32_t B, int32_t nz, int32_t ny,
                            int32_t nx, double c, float* out, void* stream);
 hgs_status hgs_nn_compose(const float* phi_c, const float* y, const float* scale, int32_t B, int64_t nvox,

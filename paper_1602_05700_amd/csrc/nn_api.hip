@@ -3,12 +3,17 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "../../include/hgs.h"
 #include "k_nn.hpp"
 
 static_assert(hgs::nn::MAXABS_CHUNKS == HGS_NN_MAXABS_CHUNKS, "scratch size of hgs_nn_maxabs");
+
+// Partials of hgs_nn_maxabs_noalloc (see scratch_on_current_device below).
+constexpr int MAXABS_NOALLOC_MAX_B = HGS_NN_MAXABS_NOALLOC_MAX_B;
+static __device__ __align__(256) float scratch[MAXABS_NOALLOC_MAX_B * hgs::nn::MAXABS_CHUNKS];  // 1 MiB per device
 
 using namespace hgs::nn;
 
@@ -37,6 +42,37 @@ int wgrad_blocks(int32_t B, int32_t Z, int32_t Y) {
 }
 
 int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256)); }
+
+// Partials of hgs_nn_maxabs_noalloc: a file-scope device array, so that the
+// call allocates nothing.  Each device holds its own copy at its own address;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name in host code is a host-side
+// stand-in, not a device address).  The kernels write every partial they read,
+// so nothing has to be cleared between calls.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device on its first use; nullptr (with the reason in g_nn_err) on failure.
+float* scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        nfail(HGS_ERR_DEVICE, "hgs_nn_maxabs_noalloc: no current HIP device");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            nfail(HGS_ERR_DEVICE, std::string("hgs_nn_maxabs_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -166,6 +202,20 @@ hgs_status hgs_nn_maxabs(const float* x, int32_t B, int64_t nvox, float* out, fl
     hipLaunchKernelGGL(k_maxabs_partial, dim3(MAXABS_CHUNKS, B), dim3(256), 0, st, x, nvox, scratch);
     hipLaunchKernelGGL(k_maxabs_final, dim3((B + 255) / 256), dim3(256), 0, st, scratch, B, out);
     return nlaunched("hgs_nn_maxabs");
+}
+
+hgs_status hgs_nn_maxabs_noalloc(const float* x, int32_t B, int64_t nvox, float* out, void* stream) {
+    if (!x || !out) return nfail(HGS_ERR_ARG, "x and out must be non-NULL");
+    if (B < 1 || B > MAXABS_NOALLOC_MAX_B || nvox < 1)
+        return nfail(HGS_ERR_ARG, "hgs_nn_maxabs_noalloc: need 1 <= B <= " + std::to_string(MAXABS_NOALLOC_MAX_B) +
+                                      " (the static scratch size) and nvox >= 1");
+    float* part = scratch_on_current_device();
+    if (!part) return HGS_ERR_DEVICE;
+    (void)hipGetLastError();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_maxabs_partial, dim3(MAXABS_CHUNKS, B), dim3(256), 0, st, x, nvox, part);
+    hipLaunchKernelGGL(k_maxabs_final, dim3((B + 255) / 256), dim3(256), 0, st, part, B, out);
+    return nlaunched("hgs_nn_maxabs_noalloc");
 }
 
 hgs_status hgs_nn_features(const float* rho, const float* phi, const float* scale, int32_t B, int32_t nz, int32_t ny,

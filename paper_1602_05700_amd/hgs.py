@@ -94,6 +94,7 @@ _SIGS = {
     "hgs_nn_unpack": (_i32, [_vp, _i32, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_mse": (_i32, [_vp, _vp, _i32, _i32, ctypes.c_int64, _vp, _vp, _vp, _vp]),
     "hgs_nn_maxabs": (_i32, [_vp, _i32, ctypes.c_int64, _vp, _vp, _vp]),
+    "hgs_nn_maxabs_noalloc": (_i32, [_vp, _i32, ctypes.c_int64, _vp, _vp]),
     "hgs_nn_features": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _dbl, _vp, _vp]),
     "hgs_nn_compose": (_i32, [_vp, _vp, _vp, _i32, ctypes.c_int64, _dbl, _vp, _vp, _vp]),
     "hgs_nn_lapmse": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, _vp, _vp, _vp, _vp,
@@ -712,6 +713,17 @@ def nn_maxabs(x, out, scratch=None):
     assert scratch.numel() >= B * NN_MAXABS_CHUNKS
     _nn_check(_lib.hgs_nn_maxabs(x.data_ptr(), B, x[0].numel(), out.data_ptr(), scratch.data_ptr(),
                                  _stream_of(x)))
+
+
+NN_MAXABS_NOALLOC_MAX_B = 4096
+
+
+def nn_maxabs_noalloc(x, out):
+    """nn_maxabs without a scratch buffer: the library's static per-device
+    partials (B <= NN_MAXABS_NOALLOC_MAX_B); allocates nothing."""
+    B = x.shape[0]
+    assert out.numel() == B and x.is_contiguous()
+    _nn_check(_lib.hgs_nn_maxabs_noalloc(x.data_ptr(), B, x[0].numel(), out.data_ptr(), _stream_of(x)))
 
 
 def nn_features(rho, phi, scale, c: float, out):

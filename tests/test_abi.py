@@ -205,3 +205,15 @@ def test_no_fallback_without_the_library(tmp_path):
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "libhgs.so" in r.stderr
+
+
+def test_noalloc_maxabs_validates_on_the_host():
+    """The allocation-free maxabs refuses NULL pointers and sample counts
+    beyond its static scratch before touching a device."""
+    L = hgs.library()
+    dummy = ctypes.c_void_p(1 << 20)
+    assert L.hgs_nn_maxabs_noalloc(None, 1, 4, dummy, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_nn_maxabs_noalloc(dummy, hgs.NN_MAXABS_NOALLOC_MAX_B + 1, 4, dummy, None) == hgs.HGS_ERR_ARG
+    assert b"static scratch" in L.hgs_nn_last_error()
+    assert L.hgs_nn_maxabs_noalloc(dummy, 0, 4, dummy, None) == hgs.HGS_ERR_ARG
+    assert L.hgs_nn_maxabs_noalloc(dummy, 1, 0, dummy, None) == hgs.HGS_ERR_ARG
