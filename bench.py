@@ -37,6 +37,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def tile_desc(storage: str, tblock: int, tile: int):
+    """The fused launch's tile as reported: index and shape (rows per thread,
+    waves, planes in flight); None when the depth has no fused launch."""
+    from paper_1602_05700_amd import hgs
+
+    if tblock < 2:
+        return None
+    r, w, pf = hgs.tile_shape(storage, tblock, tile if tile < hgs.tile_count(tblock) else 0)
+    return {"index": tile, "rows_per_thread": r, "waves": w, "planes_in_flight": pf,
+            "extended_tile": [64, r * w]}
+
+
 KERNEL_SOURCES = {
     # sources that define each timed stencil kernel (the counter file is valid
     # only while they are unchanged)
@@ -196,10 +208,10 @@ def run_configs(dev):
     for label, eta in (("eta_0", 0.0), ("eta_critical", 2.0 * math.sqrt(lam))):
         # fused depth by the library's autotuner (timed on 8-substep steps):
         # at 64^3 a fused launch is bound by its pipeline fill, not by HBM
-        tb, _ = hgs.autotune(n, rho, 1.0, dt, 8, storage="f64", lmax=0, eta=eta, device=dev)
-        s = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, device=dev)
+        tb, tile, _ = hgs.autotune(n, rho, 1.0, dt, 8, storage="f64", lmax=0, eta=eta, device=dev)
+        s = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, tile=tile, device=dev)
         s.step(rho, 1.0, dt, 8)  # warm-up
-        s2 = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, device=dev)
+        s2 = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, tile=tile, device=dev)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s2.stream)
@@ -208,7 +220,7 @@ def run_configs(dev):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         out.setdefault("sphere_64_f64", {})[label] = {
-            "substeps": 2000, "tblock": tb, "ms": round(ms, 3),
+            "substeps": 2000, "tblock": tb, "tile": tile_desc("f64", tb, tile), "ms": round(ms, 3),
             "Gcell_updates_per_s": round(n ** 3 * 2000 / (ms / 1e3) / 1e9, 2),
             "R_f": float(s2.residual(rho)[1])}
         s.close()
@@ -219,8 +231,8 @@ def run_configs(dev):
     blobs = workloads.blob_params(0, 8)
     for storage, tdt in (("f64", torch.float64), ("f32", torch.float32)):
         rhos = [workloads.blob_density_torch(n, blobs.rotated(0.1 * nsub * dt * h), dev, tdt) for h in range(64)]
-        tb, _ = hgs.autotune(n, rhos[0], 1.0, dt, nsub, storage=storage, lmax=4, eta=0.0, device=dev)
-        s = hgs.Solver(n, storage=storage, lmax=4, eta=0.0, tblock=tb, device=dev)
+        tb, tile, _ = hgs.autotune(n, rhos[0], 1.0, dt, nsub, storage=storage, lmax=4, eta=0.0, device=dev)
+        s = hgs.Solver(n, storage=storage, lmax=4, eta=0.0, tblock=tb, tile=tile, device=dev)
         g = [torch.empty((n, n, n), dtype=tdt, device=dev) for _ in range(3)]
         for h in range(3):
             s.step(rhos[h], 1.0, dt, nsub)
@@ -238,7 +250,8 @@ def run_configs(dev):
         kinds = {k: s.timing_read(k) for k in ("stencil", "multipole", "gradient")}
         s.timing(False)
         out.setdefault("rotating_256", {})[storage] = {
-            "hydro_steps": steps, "tblock": s.tblock, "ms_per_hydro_step": round(ms / steps, 4),
+            "hydro_steps": steps, "tblock": s.tblock, "tile": tile_desc(storage, s.tblock, s.tile),
+            "ms_per_hydro_step": round(ms / steps, 4),
             "Gcell_updates_per_s": round(n ** 3 * nsub * steps / (ms / 1e3) / 1e9, 2),
             "us_per_launch": {k: round(d["ms"] / max(d["launches"], 1) * 1e3, 1) for k, d in kinds.items()},
             "stencil_GBps_algorithmic": round(kinds["stencil"]["bytes"] / kinds["stencil"]["ms"] / 1e6, 0)}
@@ -488,6 +501,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--nsub", type=int, default=4)
     ap.add_argument("--tblock", type=int, default=0, help="substeps per fused launch (0 = autotune)")
+    ap.add_argument("--tile", type=int, default=0, help="tile shape index with --tblock (hgs_tile_shape)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched measurement")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the steps-to-1e-4 warm-start measurement")
@@ -529,13 +543,13 @@ def main():
     rhos = [workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * h), dev, torch.float32)
             for h in range(W + K)]
     tune = None
-    tblock = args.tblock
+    tblock, tile = args.tblock, args.tile
     if tblock == 0:
-        best, times = hgs.autotune(n, rhos[0], c_g, dt, nsub, storage="f32", lmax=4, device=dev)
-        tune = {"best_tblock": best, "ms_per_substep": times}
-        tblock = best
-        log(f"[bench] autotune: depth {best}, ms per substep {times}")
-    s = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=tblock, device=dev)
+        best, best_tile, times = hgs.autotune(n, rhos[0], c_g, dt, nsub, storage="f32", lmax=4, device=dev)
+        tune = {"best_tblock": best, "best_tile": tile_desc("f32", best, best_tile), "ms_per_substep": times}
+        tblock, tile = best, best_tile
+        log(f"[bench] autotune: depth {best}, tile {tune['best_tile']}, ms per substep {times}")
+    s = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=tblock, tile=tile, device=dev)
     out = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in range(3)]
     stream = s.stream
     # start: the converged potential of the first density (critically damped
@@ -608,7 +622,8 @@ def main():
             "workload": f"hyperbolic gravity, {n}^3 grid, 16 rotating Gaussian blobs, FP32 storage, lmax 4, "
                         f"{nsub} substeps per hydro step, moments+ghosts+substeps+gradient, from the converged "
                         "potential with the rotation's time derivative",
-            "grid": n, "nsub": nsub, "tblock": s.tblock, "lmax": 4, "blobs": 16,
+            "grid": n, "nsub": nsub, "tblock": s.tblock, "tile": tile_desc("f32", s.tblock, s.tile), "lmax": 4,
+            "blobs": 16,
         },
         "roofline": {
             "bound": "hbm",

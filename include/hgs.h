@@ -284,6 +284,23 @@ hgs_status hgs_load_raw(hgs_ctx* ctx, const void* phi_n, const void* phi_nm1, do
 hgs_status hgs_set_tblock(hgs_ctx* ctx, int32_t tblock);
 int32_t hgs_get_tblock(const hgs_ctx* ctx);
 
+/* Tile shape of the fused launches.  A fused launch of depth T gives each
+ * workgroup an (x, y) tile that it marches up a chunk of z planes; several
+ * shapes are compiled per storage type and depth, trading the tile's height
+ * (less halo recomputed and re-read per cell) against the input planes kept
+ * in flight (both live in registers).  Results are bit-identical for every
+ * shape.  hgs_tile_count(T): shapes compiled for depth T (0 for T outside
+ * 2..HGS_TMAX).  hgs_tile_shape: shape[0] rows per thread, shape[1] waves per
+ * workgroup (the tile is 64 x rows*waves cells, T of them halo on each side),
+ * shape[2] input planes in flight; HGS_ERR_ARG for an unknown storage, depth
+ * or index.  hgs_set_tile selects index tile (0 = default) for later steps;
+ * a depth with fewer shapes uses its shape 0.  HGS_ERR_ARG if tile is outside
+ * 0..hgs_tile_count(HGS_TMAX)-1. */
+int32_t hgs_tile_count(int32_t tblock);
+hgs_status hgs_tile_shape(int32_t storage, int32_t tblock, int32_t tile, int32_t shape[3]);
+hgs_status hgs_set_tile(hgs_ctx* ctx, int32_t tile);
+int32_t hgs_get_tile(const hgs_ctx* ctx);
+
 /* Per-launch timing with HIP events recorded on the context's stream around
  * each kernel launch of the given kind, for roofline measurements:
  *   HGS_KERNEL_STENCIL  the substep launches of hgs_step (streaming or fused),
@@ -424,17 +441,21 @@ hgs_status hgs_nn_prolong2(const void* coarse, void* fine, int32_t B, int32_t cz
 const char* hgs_nn_last_error(void);
 
 /* ---- Autotuner -------------------------------------------------------------
- * Picks the fused depth (substeps per stencil launch) for a configuration by
- * timing whole hydrodynamical steps, hgs_step(rho, c_g, dt, nsub), with HIP
- * events for every depth 1..HGS_TMAX on a temporary context built over the
- * caller's workspace (hgs_workspace_bytes(cfg) bytes; its contents are
- * overwritten).  Synchronises.  *best_tblock receives the fastest depth;
- * ms_per_substep (nullable, HGS_TMAX entries) the measured time per substep for
- * depths 1..HGS_TMAX.  If the environment variable HGS_TUNE_CACHE names a
- * file, results are cached there per (device architecture, nx, ny, nz, storage,
- * nsub, bc) and a cached entry is returned without timing (times set to -1). */
+ * Picks the fused depth (substeps per stencil launch) and the tile shape for a
+ * configuration by timing whole hydrodynamical steps, hgs_step(rho, c_g, dt,
+ * nsub), with HIP events for every depth 1..HGS_TMAX and every tile shape
+ * compiled for it, on a temporary context built over the caller's workspace
+ * (hgs_workspace_bytes(cfg) bytes; its contents are overwritten).
+ * Synchronises.  *best_tblock receives the fastest depth, *best_tile
+ * (nullable) its tile index (for hgs_set_tile); ms_per_substep (nullable,
+ * HGS_TMAX entries) the best measured time per substep for each depth
+ * 1..HGS_TMAX.  If the environment variable HGS_TUNE_CACHE names a file,
+ * results are cached there per (device architecture, nx, ny, nz, storage,
+ * nsub, bc) as (depth, tile) and a cached entry is returned without timing
+ * (times set to -1). */
 hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, double c_g, double dt, int32_t nsub,
-                        void* workspace, size_t bytes, int32_t* best_tblock, double* ms_per_substep);
+                        void* workspace, size_t bytes, int32_t* best_tblock, int32_t* best_tile,
+                        double* ms_per_substep);
 
 /* Release the host context (the workspace stays the caller's).  NULL is a no-op. */
 hgs_status hgs_destroy(hgs_ctx* ctx);

@@ -50,6 +50,7 @@ struct hgs_ctx {
     double dt_prev;
     bool have_moments;
     int tblock;
+    int tile;  // tile shape of the fused launches (index into TileSet)
     int ncu;  // compute units of the device
     std::string err;
     // launch timing (hgs_timing_*)
@@ -388,7 +389,7 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
                         o1 = k;
                 }
             Timed tm(c, HGS_KERNEL_STENCIL);
-            launch_tblock<S>(B<S>(c, c->cur), B<S>(c, c->old), r, B<S>(c, o0), B<S>(c, o1), c->L, sc, T, c->ncu,
+            launch_tblock<S>(B<S>(c, c->cur), B<S>(c, c->old), r, B<S>(c, o0), B<S>(c, o1), c->L, sc, T, c->tile, c->ncu,
                              c->stream);
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(5.0 * sizeof(S) * cells, cells * T);
@@ -590,7 +591,7 @@ int default_tblock(const hgs_config* cfg) { return cfg->tblock > 0 ? cfg->tblock
 
 extern "C" {
 
-int32_t hgs_abi_version(void) { return 1; }
+int32_t hgs_abi_version(void) { return 2; }
 
 const char* hgs_status_str(hgs_status s) {
     switch (s) {
@@ -667,6 +668,7 @@ hgs_status hgs_init(const hgs_config* cfg, void* workspace, size_t bytes, hgs_ct
     c->dt_prev = 0.0;
     c->have_moments = false;
     c->tblock = default_tblock(cfg);
+    c->tile = 0;
     c->timing = false;
     c->pool_used = 0;
     {
@@ -741,6 +743,35 @@ hgs_status hgs_set_tblock(hgs_ctx* ctx, int32_t tblock) {
 }
 
 int32_t hgs_get_tblock(const hgs_ctx* ctx) { return ctx ? ctx->tblock : 0; }
+
+int32_t hgs_tile_count(int32_t tblock) { return tblock >= 2 && tblock <= HGS_TMAX ? tile_count(tblock) : 0; }
+
+hgs_status hgs_tile_shape(int32_t storage, int32_t tblock, int32_t tile, int32_t shape[3]) {
+    if (!shape) return fail(nullptr, HGS_ERR_ARG, "shape is NULL");
+    if (storage != HGS_F32 && storage != HGS_F64) return fail(nullptr, HGS_ERR_ARG, "storage must be HGS_F32 or HGS_F64");
+    if (tblock < 2 || tblock > HGS_TMAX) return fail(nullptr, HGS_ERR_ARG, "tblock must be in 2..4");
+    if (tile < 0 || tile >= tile_count(tblock)) return fail(nullptr, HGS_ERR_ARG, "no such tile for this depth");
+    TileShape t{0, 0, 0};
+    const bool f32 = storage == HGS_F32;
+    switch (tblock) {
+        case 2: t = f32 ? TileSet<float, 2>::at(tile) : TileSet<double, 2>::at(tile); break;
+        case 3: t = f32 ? TileSet<float, 3>::at(tile) : TileSet<double, 3>::at(tile); break;
+        default: t = f32 ? TileSet<float, 4>::at(tile) : TileSet<double, 4>::at(tile); break;
+    }
+    shape[0] = t.R;
+    shape[1] = t.W;
+    shape[2] = t.PF;
+    return HGS_OK;
+}
+
+hgs_status hgs_set_tile(hgs_ctx* ctx, int32_t tile) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (tile < 0 || tile >= tile_count(HGS_TMAX)) return fail(ctx, HGS_ERR_ARG, "tile out of range");
+    ctx->tile = tile;
+    return HGS_OK;
+}
+
+int32_t hgs_get_tile(const hgs_ctx* ctx) { return ctx ? ctx->tile : 0; }
 
 static hgs_status validate_step(hgs_ctx* ctx, const hgs_config* cfg, const void* rho, double c_g, double dt,
                                 int32_t nsub) {
@@ -1135,9 +1166,9 @@ void batch_items(const std::vector<Layout>& Ls, int T, int zchunk, std::vector<W
         if (T > 1) {
             int IX = 64 - 2 * T, IY = 0;
             switch (T) {
-                case 2: IY = TBConfig<S, 2>::W * TBConfig<S, 2>::R - 4; break;
-                case 3: IY = TBConfig<S, 3>::W * TBConfig<S, 3>::R - 6; break;
-                default: IY = TBConfig<S, 4>::W * TBConfig<S, 4>::R - 8; break;
+                case 2: IY = BatchTile<S, 2>::W * BatchTile<S, 2>::R - 4; break;
+                case 3: IY = BatchTile<S, 3>::W * BatchTile<S, 3>::R - 6; break;
+                default: IY = BatchTile<S, 4>::W * BatchTile<S, 4>::R - 8; break;
             }
             const int tx = (L.nx + IX - 1) / IX, ty = (L.ny + IY - 1) / IY;
             const int zc = std::min(L.nz, zchunk);
@@ -1282,18 +1313,21 @@ void batch_launches(hgs_batch* b, int nsub, int cur, int old, hipStream_t st) {
             const int nb = std::min(b->n_tb_items, ncu);
             switch (T) {
                 case 2:
-                    hipLaunchKernelGGL((k_tblock_batch<S, 2, TBConfig<S, 2>::R, TBConfig<S, 2>::W>), dim3(nb),
-                                       dim3(64 * TBConfig<S, 2>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
+                    hipLaunchKernelGGL((k_tblock_batch<S, 2, BatchTile<S, 2>::R, BatchTile<S, 2>::W, BatchTile<S, 2>::PF,
+                                                        BatchTile<S, 2>::SB, BatchTile<S, 2>::UPF>),
+                                       dim3(nb), dim3(64 * BatchTile<S, 2>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
                                        o0, o1);
                     break;
                 case 3:
-                    hipLaunchKernelGGL((k_tblock_batch<S, 3, TBConfig<S, 3>::R, TBConfig<S, 3>::W>), dim3(nb),
-                                       dim3(64 * TBConfig<S, 3>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
+                    hipLaunchKernelGGL((k_tblock_batch<S, 3, BatchTile<S, 3>::R, BatchTile<S, 3>::W, BatchTile<S, 3>::PF,
+                                                        BatchTile<S, 3>::SB, BatchTile<S, 3>::UPF>),
+                                       dim3(nb), dim3(64 * BatchTile<S, 3>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
                                        o0, o1);
                     break;
                 default:
-                    hipLaunchKernelGGL((k_tblock_batch<S, 4, TBConfig<S, 4>::R, TBConfig<S, 4>::W>), dim3(nb),
-                                       dim3(64 * TBConfig<S, 4>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
+                    hipLaunchKernelGGL((k_tblock_batch<S, 4, BatchTile<S, 4>::R, BatchTile<S, 4>::W, BatchTile<S, 4>::PF,
+                                                        BatchTile<S, 4>::SB, BatchTile<S, 4>::UPF>),
+                                       dim3(nb), dim3(64 * BatchTile<S, 4>::W), 0, st, d, b->tb_items, b->n_tb_items, cur, old,
                                        o0, o1);
                     break;
             }
@@ -1533,35 +1567,45 @@ std::string tune_key(const hgs_config* cfg, int nsub) {
     return k.str();
 }
 
-// cache file: one "<key> <tblock>" entry per line
-int tune_cache_lookup(const std::string& path, const std::string& key) {
+// cache file: one "<key> <tblock> <tile>" entry per line (an entry without a
+// tile means tile 0)
+bool tune_cache_lookup(const std::string& path, const std::string& key, int& t_out, int& tile_out) {
     std::ifstream f(path);
     std::string line;
-    int best = 0;
+    bool found = false;
     while (std::getline(f, line)) {
         if (line.size() > key.size() && line.compare(0, key.size(), key) == 0 && line[key.size()] == ' ') {
-            const int t = std::atoi(line.c_str() + key.size() + 1);
-            if (t >= 1 && t <= HGS_TMAX) best = t;  // last entry wins
+            std::istringstream v(line.substr(key.size() + 1));
+            int t = 0, tile = 0;
+            v >> t;
+            if (!(v >> tile)) tile = 0;
+            if (t >= 1 && t <= HGS_TMAX && tile >= 0 && tile < (t >= 2 ? tile_count(t) : 1)) {  // last entry wins
+                t_out = t;
+                tile_out = tile;
+                found = true;
+            }
         }
     }
-    return best;
+    return found;
 }
 
-void tune_cache_store(const std::string& path, const std::string& key, int t) {
+void tune_cache_store(const std::string& path, const std::string& key, int t, int tile) {
     std::ofstream f(path, std::ios::app);
-    if (f) f << key << ' ' << t << '\n';
+    if (f) f << key << ' ' << t << ' ' << tile << '\n';
 }
 
 }  // namespace
 
 extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, double c_g, double dt, int32_t nsub,
-                                   void* workspace, size_t bytes, int32_t* best_tblock, double* ms_per_substep) {
+                                   void* workspace, size_t bytes, int32_t* best_tblock, int32_t* best_tile,
+                                   double* ms_per_substep) {
     std::string why;
     hgs_status s = check_config(cfg, why);
     if (s != HGS_OK) return fail(nullptr, s, why);
     if (!best_tblock) return fail(nullptr, HGS_ERR_ARG, "best_tblock is NULL");
     s = validate_step(nullptr, cfg, rho, c_g, dt, nsub);
     if (s != HGS_OK) return s;
+    if (best_tile) *best_tile = 0;
     if (local_bc(cfg->bc)) {  // one substep per launch: nothing to choose
         *best_tblock = 1;
         if (ms_per_substep)
@@ -1571,9 +1615,10 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
     const char* cache = std::getenv("HGS_TUNE_CACHE");
     const std::string key = tune_key(cfg, nsub);
     if (cache && *cache) {
-        const int t = tune_cache_lookup(cache, key);
-        if (t > 0) {
+        int t = 0, tile = 0;
+        if (tune_cache_lookup(cache, key, t, tile)) {
             *best_tblock = t;
+            if (best_tile) *best_tile = tile;
             if (ms_per_substep)
                 for (int i = 0; i < HGS_TMAX; ++i) ms_per_substep[i] = -1.0;
             return HGS_OK;
@@ -1589,27 +1634,37 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
     }
     const int reps = 3;
     double best_ms = -1.0;
-    int best = 1;
+    int best = 1, best_t = 0;
     hgs_status st = HGS_OK;
+    // every depth 1..HGS_TMAX, and every tile shape compiled for a depth; a
+    // depth whose fused launch nsub never reaches (T > nsub) is timed as well,
+    // it then runs streaming substeps only
     for (int t = 1; t <= HGS_TMAX && st == HGS_OK; ++t) {
-        c->tblock = t;
-        st = hgs_step(c, rho, c_g, dt, nsub);  // warm-up
-        if (st != HGS_OK) break;
-        (void)hipEventRecord(e0, c->stream);
-        for (int r = 0; r < reps && st == HGS_OK; ++r) st = hgs_step(c, rho, c_g, dt, nsub);
-        (void)hipEventRecord(e1, c->stream);
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            st = fail(nullptr, HGS_ERR_DEVICE, "hgs_autotune: timing failed");
-            break;
+        const int ntile = t >= 2 ? tile_count(t) : 1;
+        double best_here = -1.0;
+        for (int tile = 0; tile < ntile && st == HGS_OK; ++tile) {
+            c->tblock = t;
+            c->tile = tile;
+            st = hgs_step(c, rho, c_g, dt, nsub);  // warm-up
+            if (st != HGS_OK) break;
+            (void)hipEventRecord(e0, c->stream);
+            for (int r = 0; r < reps && st == HGS_OK; ++r) st = hgs_step(c, rho, c_g, dt, nsub);
+            (void)hipEventRecord(e1, c->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(nullptr, HGS_ERR_DEVICE, "hgs_autotune: timing failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double per = (double)ms / (reps * nsub);
+            if (best_here < 0.0 || per < best_here) best_here = per;
+            if (best_ms < 0.0 || per < best_ms) {
+                best_ms = per;
+                best = t;
+                best_t = tile;
+            }
         }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double per = (double)ms / (reps * nsub);
-        if (ms_per_substep) ms_per_substep[t - 1] = per;
-        if (best_ms < 0.0 || per < best_ms) {
-            best_ms = per;
-            best = t;
-        }
+        if (ms_per_substep) ms_per_substep[t - 1] = best_here;
     }
     if (st != HGS_OK && c) g_err = c->err;
     (void)hipEventDestroy(e0);
@@ -1617,6 +1672,7 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
     hgs_destroy(c);
     if (st != HGS_OK) return st;
     *best_tblock = best;
-    if (cache && *cache) tune_cache_store(cache, key, best);
+    if (best_tile) *best_tile = best_t;
+    if (cache && *cache) tune_cache_store(cache, key, best, best_t);
     return HGS_OK;
 }

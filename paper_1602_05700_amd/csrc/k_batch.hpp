@@ -28,14 +28,24 @@ struct WorkItem {
     int grid, tx, ty, k0, k1;
 };
 
+// tile shape of the batched fused launches: the default shape of each depth
+template <typename S, int T>
+struct BatchTile {
+    static constexpr int R = TileSet<S, T>::at(0).R;
+    static constexpr int W = TileSet<S, T>::at(0).W;
+    static constexpr int PF = TileSet<S, T>::at(0).PF;
+    static constexpr bool SB = TileSet<S, T>::at(0).SB;
+    static constexpr bool UPF = TileSet<S, T>::at(0).UPF;
+};
+
 // T fused substeps on every grid: (buf[in0], buf[in1]) -> (buf[out0], buf[out1])
-template <typename S, int T, int R, int W>
+template <typename S, int T, int R, int W, int PF, bool SB, bool UPF>
 __global__ __launch_bounds__(64 * W) void k_tblock_batch(const GridDesc<S>* __restrict__ grids,
                                                          const WorkItem* __restrict__ items, int nitems, int in0,
                                                          int in1, int out0, int out1) {
     constexpr int IX = 64 - 2 * T;
     constexpr int IY = W * R - 2 * T;
-    __shared__ TBShared<S, T, R, W> sh;
+    __shared__ TBShared<S, T, W> sh;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const WorkItem wi = items[it];
         const GridDesc<S>& g = grids[wi.grid];
@@ -44,11 +54,11 @@ __global__ __launch_bounds__(64 * W) void k_tblock_batch(const GridDesc<S>* __re
         const int xlo = wi.tx * IX - T, ylo = wi.ty * IY - T;
         const bool inner = xlo >= 0 && xlo + 64 <= L.nx && ylo >= 0 && ylo + W * R <= L.ny;
         if (inner) {
-            TBTile<S, T, R, W, false> t(g.buf[in0], g.buf[in1], g.rho, g.buf[out0], g.buf[out1], L, c, sh, wi.tx,
+            TBTile<S, T, R, W, PF, SB, UPF, false> t(g.buf[in0], g.buf[in1], g.rho, g.buf[out0], g.buf[out1], L, c, sh, wi.tx,
                                         wi.ty, wi.k0, wi.k1);
             t.run();
         } else {
-            TBTile<S, T, R, W, true> t(g.buf[in0], g.buf[in1], g.rho, g.buf[out0], g.buf[out1], L, c, sh, wi.tx,
+            TBTile<S, T, R, W, PF, SB, UPF, true> t(g.buf[in0], g.buf[in1], g.rho, g.buf[out0], g.buf[out1], L, c, sh, wi.tx,
                                        wi.ty, wi.k0, wi.k1);
             t.run();
         }

@@ -24,10 +24,13 @@
 // value at every level.  Every level is rounded to the storage type exactly as
 // a streaming launch stores it, so any T gives bit-identical results.
 //
-// The plane loop is unrolled by U = lcm(3, 2, T) so that the three-plane
-// windows, the LDS slot parity and the ring of rho planes rotate by
-// compile-time index instead of register moves.  Tiles whose extended region
-// lies inside the grid take a path without per-cell boundary selects.
+// The plane loop is unrolled by U = lcm(3, 2, T, PF) so that the three-plane
+// windows, the LDS slot parity, the ring of rho planes and the prefetch ring
+// rotate by compile-time index instead of register moves.  Tiles whose
+// extended region lies inside the grid take a path without per-cell x/y
+// boundary selects.  The tile shape (rows per thread, waves, planes in
+// flight) is a template parameter; several shapes are compiled and the
+// autotuner picks one.
 #pragma once
 
 #include "common.hpp"
@@ -46,57 +49,73 @@ __device__ __forceinline__ float lane_next(float v) {
 __device__ __forceinline__ double lane_prev(double v) { return __shfl_up(v, 1, 64); }
 __device__ __forceinline__ double lane_next(double v) { return __shfl_down(v, 1, 64); }
 
-template <int T>
+// Plane-loop unroll: lcm(3, 2, T, PF), so that the three-plane windows, the
+// LDS slot parity, the ring of rho planes and the prefetch ring all rotate by
+// compile-time index.
+constexpr int tb_gcd(int a, int b) { return b == 0 ? a : tb_gcd(b, a % b); }
+constexpr int tb_lcm(int a, int b) { return a / tb_gcd(a, b) * b; }
+template <int T, int PF>
 struct Unroll {
-    static constexpr int U = (T == 4) ? 12 : 6;  // lcm(3, 2, T, prefetch depth 3)
+    static constexpr int U = tb_lcm(tb_lcm(6, T), PF);
 };
-// Input planes loaded ahead: one plane step keeps a SIMD busy for about a
-// microsecond, so three planes in flight cover the HBM latency under load
-// (measured at 512^3: 4% faster than two).
-constexpr int PF = 3;
 
-template <typename S, int T, int R, int W>
+template <typename S, int T, int W>
 struct TBShared {
     S edge[T][2][W][2][64];  // [level][slot][wave][0 first row, 1 last row][lane]
 };
 
-template <typename S, int T, int R, int W, bool EDGE>
+// PF: input planes loaded ahead (the prefetch ring, in registers).
+// SB: addresses as a uniform plane base plus a 32-bit byte offset kept in the
+//     block of each access (no per-access 64-bit address arithmetic), else a
+//     64-bit address per access.
+// UPF: prefetch loads issued unconditionally (past the chunk's end the
+//     clamped loads read planes that are never used: no branch and no ring
+//     copies), else only while planes remain.
+// Which is faster depends on the shape and depth (measured; see TileSet).
+template <typename S, int T, int R, int W, int PF, bool SB, bool UPF, bool EDGE>
 struct TBTile {
     static constexpr int IX = 64 - 2 * T;
     static constexpr int IY = W * R - 2 * T;
-    static constexpr int U = Unroll<T>::U;
+    static constexpr int U = Unroll<T, PF>::U;
 
-    // per-thread constants
+    // uniform values (scalar registers)
     const S* in_n;
     const S* in_nm1;
     const S* rho;
     S* out_n;
     S* out_nm1;
-    const Layout& L;
     const StepCoef& c;
-    TBShared<S, T, R, W>& sh;
-    int lane, w, x, y0, k0, k1, wm, wp;
-    int off_p[R];  // lane offsets within a padded plane (clamped to the ghost box)
-    int off_c[R];  // lane offsets within a compact rho plane (clamped to the interior)
-    bool x_in, y_in[R], in_ok[R], out_ok[R];
+    TBShared<S, T, W>& sh;
+    int64_t plane, cplane;  // elements per padded / compact plane
+    int nz, k0, k1;
+    // per-thread constants.  Addresses are a uniform plane base plus a 32-bit
+    // byte offset, so loads and stores take the scalar-base form and need no
+    // per-access 64-bit address arithmetic.
+    int lane, w, wm, wp;
+    uint32_t bp[R];  // byte offsets within a padded plane (clamped to the ghost box)
+    uint32_t bc[R];  // byte offsets within a compact rho plane (clamped to the interior)
+    bool in_ok[R], out_ok[R];
 
     // pipeline state
     S win[T][3][R];  // [level][ring slot][row]
     S rq[T][R];      // ring of rho planes
     S pn[PF][R], po[PF][R], pr[PF][R];  // prefetch ring
 
-    __device__ TBTile(const S* a, const S* b, const S* rh, S* o0, S* o1, const Layout& Ly, const StepCoef& cc,
-                      TBShared<S, T, R, W>& s, int tx, int ty, int kk0, int kk1)
-        : in_n(a), in_nm1(b), rho(rh), out_n(o0), out_nm1(o1), L(Ly), c(cc), sh(s) {
+    __device__ TBTile(const S* a, const S* b, const S* rh, S* o0, S* o1, const Layout& L, const StepCoef& cc,
+                      TBShared<S, T, W>& s, int tx, int ty, int kk0, int kk1)
+        : in_n(a), in_nm1(b), rho(rh), out_n(o0), out_nm1(o1), c(cc), sh(s) {
+        plane = L.plane;
+        cplane = (int64_t)L.nx * L.ny;
+        nz = L.nz;
         lane = threadIdx.x & 63;
         w = threadIdx.x >> 6;
-        x = tx * IX - T + lane;
-        y0 = ty * IY - T + w * R;
+        const int x = tx * IX - T + lane;
+        const int y0 = ty * IY - T + w * R;
         k0 = kk0;
         k1 = kk1;
         wm = w > 0 ? w - 1 : 0;
         wp = w < W - 1 ? w + 1 : W - 1;
-        x_in = x >= 0 && x < L.nx;
+        const bool x_in = x >= 0 && x < L.nx;
         const bool x_out = x_in && lane >= T && lane < T + IX;
         const int xc = min(max(x, -1), L.nx);
         const int xr = min(max(x, 0), L.nx - 1);
@@ -104,13 +123,13 @@ struct TBTile {
         for (int r = 0; r < R; ++r) {
             const int y = y0 + r;
             const int er = w * R + r;
-            y_in[r] = y >= 0 && y < L.ny;
-            in_ok[r] = x_in && y_in[r];
-            out_ok[r] = x_out && y_in[r] && er >= T && er < T + IY;
+            const bool y_in = y >= 0 && y < L.ny;
+            in_ok[r] = x_in && y_in;
+            out_ok[r] = x_out && y_in && er >= T && er < T + IY;
             const int yc = min(max(y, -1), L.ny);
             const int yr = min(max(y, 0), L.ny - 1);
-            off_p[r] = (yc + HALO) * L.pitch + (xc + L.xoff);
-            off_c[r] = yr * L.nx + xr;
+            bp[r] = (uint32_t)(((yc + HALO) * L.pitch + (xc + L.xoff)) * (int)sizeof(S));
+            bc[r] = (uint32_t)((yr * L.nx + xr) * (int)sizeof(S));
         }
 #pragma unroll
         for (int t = 0; t < T; ++t)
@@ -121,6 +140,13 @@ struct TBTile {
             }
     }
 
+    __device__ __forceinline__ static S at(const S* base, uint32_t off) {
+        return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off);
+    }
+    __device__ __forceinline__ static void put(S* base, uint32_t off, S v) {
+        *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + off) = v;
+    }
+
     // inputs of plane p: phi^n(p), phi^{n-1}(p-1), rho(p-1), into ring slot B.
     // Loads are never predicated: plane and lane offsets are clamped into the
     // ghost box (the interior for rho), and every value read that way lands in
@@ -128,16 +154,20 @@ struct TBTile {
     // valid cell.
     template <int B>
     __device__ __forceinline__ void load(int p) {
-        const int pc = min(max(p, -1), L.nz);
-        const int qc = min(max(p - 1, 0), L.nz - 1);
-        const S* bn = in_n + (int64_t)(pc + HALO) * L.plane;
-        const S* bo = in_nm1 + (int64_t)(qc + HALO) * L.plane;
-        const S* br = rho + (int64_t)qc * L.nx * L.ny;
+        const int pc = min(max(p, -1), nz);
+        const int qc = min(max(p - 1, 0), nz - 1);
+        const S* bn = in_n + (int64_t)(pc + HALO) * plane;
+        const S* bo = in_nm1 + (int64_t)(qc + HALO) * plane;
+        const S* br = rho + (int64_t)qc * cplane;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            pn[B][r] = bn[off_p[r]];
-            po[B][r] = bo[off_p[r]];
-            pr[B][r] = br[off_c[r]];
+            // SB: keep the 32-bit offsets in this block so the loads take the
+            // scalar-base form (no 64-bit address per access)
+            uint32_t op = bp[r], oc = bc[r];
+            if (SB) asm("" : "+v"(op), "+v"(oc));
+            pn[B][r] = at(bn, op);
+            po[B][r] = at(bo, op);
+            pr[B][r] = at(br, oc);
         }
     }
 
@@ -154,47 +184,50 @@ struct TBTile {
             old1[r] = po[B][r];
             rq[PH % T][r] = pr[B][r];
         }
-        if (p + PF < pend) load<B>(p + PF);
+        if (UPF || p + PF < pend) load<B>(p + PF);
         __syncthreads();  // LDS writes of plane p-1 are visible; its reads are done
         sh.edge[0][SLOT][w][0][lane] = win[0][NEW][0];
         sh.edge[0][SLOT][w][1][lane] = win[0][NEW][R - 1];
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
             const int q = p - t;
-            const bool z_in = q >= 0 && q < L.nz;
             // level t-1 holds plane q in MID, q+1 in NEW, q-1 in OLD; level t-2
-            // holds plane q in OLD (its NEW is q+2)
+            // holds plane q in OLD (its NEW is q+2).  Planes outside the grid
+            // (the ghost plane and the clamped ring below and above it) keep
+            // their input value (a select on a uniform condition).
+            const bool z_in = q >= 0 && q < nz;
             S nv[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const S ce = win[t - 1][MID][r];
-                const S zm = win[t - 1][OLD][r];
-                const S zp = win[t - 1][NEW][r];
-                const S ym = (r > 0) ? win[t - 1][MID][r - 1] : sh.edge[t - 1][PREV][wm][1][lane];
-                const S yp = (r < R - 1) ? win[t - 1][MID][r + 1] : sh.edge[t - 1][PREV][wp][0][lane];
-                const S xm = (S)lane_prev(ce);
-                const S xp = (S)lane_next(ce);
-                const S ol = (t == 1) ? old1[r] : win[t >= 2 ? t - 2 : 0][OLD][r];
-                const int RS = ((PH - t + 1) % T + T) % T;  // ring slot of rho(p - t)
-                const S v = (S)update(c, ce, xm, xp, ym, yp, zm, zp, ol, rq[RS][r]);
-                if (EDGE)
-                    nv[r] = (in_ok[r] && z_in) ? v : ce;
-                else
-                    nv[r] = z_in ? v : ce;
-            }
+                for (int r = 0; r < R; ++r) {
+                    const S ce = win[t - 1][MID][r];
+                    const S zm = win[t - 1][OLD][r];
+                    const S zp = win[t - 1][NEW][r];
+                    const S ym = (r > 0) ? win[t - 1][MID][r - 1] : sh.edge[t - 1][PREV][wm][1][lane];
+                    const S yp = (r < R - 1) ? win[t - 1][MID][r + 1] : sh.edge[t - 1][PREV][wp][0][lane];
+                    const S xm = (S)lane_prev(ce);
+                    const S xp = (S)lane_next(ce);
+                    const S ol = (t == 1) ? old1[r] : win[t >= 2 ? t - 2 : 0][OLD][r];
+                    const int RS = ((PH - t + 1) % T + T) % T;  // ring slot of rho(p - t)
+                    const S v = (S)update(c, ce, xm, xp, ym, yp, zm, zp, ol, rq[RS][r]);
+                    nv[r] = (EDGE ? (in_ok[r] && z_in) : z_in) ? v : ce;
+                }
             if (t < T) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) win[t][NEW][r] = nv[r];
                 sh.edge[t][SLOT][w][0][lane] = nv[0];
                 sh.edge[t][SLOT][w][1][lane] = nv[R - 1];
             } else if (q >= k0 && q < k1) {
-                S* on = out_n + (int64_t)(q + HALO) * L.plane;
-                S* oo = out_nm1 + (int64_t)(q + HALO) * L.plane;
+                S* on = out_n + (int64_t)(q + HALO) * plane;
+                S* oo = out_nm1 + (int64_t)(q + HALO) * plane;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (out_ok[r]) {
-                        on[off_p[r]] = nv[r];
-                        oo[off_p[r]] = win[T - 1][MID][r];
+                        uint32_t o = bp[r];
+                        // SB: keep the 32-bit offset in this block so the
+                        // stores take the scalar-base form like the loads
+                        if (SB) asm("" : "+v"(o));
+                        put(on, o, nv[r]);
+                        put(oo, o, win[T - 1][MID][r]);
                     }
                 }
             }
@@ -211,17 +244,24 @@ struct TBTile {
         return true;
     }
 
+    // the first PF input planes, from p0 on
+    template <int B>
+    __device__ __forceinline__ void prime(int p0) {
+        if constexpr (B < PF) {
+            load<B>(p0 + B);
+            prime<B + 1>(p0);
+        }
+    }
+
     __device__ void run() {
         const int pend = k1 + T;
-        load<0>(k0 - T);
-        load<1>(k0 - T + 1);
-        load<2>(k0 - T + 2);
+        prime<0>(k0 - T);
         for (int p = k0 - T; p < pend; p += U)
             if (!run_from<0>(p, pend)) break;
     }
 };
 
-template <typename S, int T, int R, int W>
+template <typename S, int T, int R, int W, int PF, bool SB, bool UPF>
 __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict__ in_n, const S* __restrict__ in_nm1,
                                                             const S* __restrict__ rho, S* __restrict__ out_n,
                                                             S* __restrict__ out_nm1, Layout L, StepCoef c, int zc,
@@ -229,7 +269,7 @@ __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict_
     constexpr int IX = 64 - 2 * T;
     constexpr int IY = W * R - 2 * T;
     static_assert(IX > 0 && IY > 0, "tile too small for the temporal depth");
-    __shared__ TBShared<S, T, R, W> sh;
+    __shared__ TBShared<S, T, W> sh;
     // tiles vary fastest and z chunks slowest, so the workgroups resident at
     // one time are neighbours at the same heights and share halo lines in L2
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -242,10 +282,10 @@ __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict_
     const int xlo = tx * IX - T, ylo = ty * IY - T;
     const bool inner = xlo >= 0 && xlo + 64 <= L.nx && ylo >= 0 && ylo + W * R <= L.ny;
     if (inner) {
-        TBTile<S, T, R, W, false> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1);
+        TBTile<S, T, R, W, PF, SB, UPF, false> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1);
         t.run();
     } else {
-        TBTile<S, T, R, W, true> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1);
+        TBTile<S, T, R, W, PF, SB, UPF, true> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1);
         t.run();
     }
 }
@@ -283,36 +323,79 @@ inline TBlockDims tblock_dims(const Layout& L, int slots) {
     return d;
 }
 
-// Tile shape (R rows per thread, W waves per workgroup) per storage type and
-// depth, chosen by measurement on MI355X at 512^3 and bounded by registers:
-// every level keeps three planes per cell in registers.  FP32: 16 waves of
-// 2 rows (extended tile 64 x 32; 112 VGPRs at T = 4, so the 16 waves fit one
-// CU): as fast as 8 waves of 4 rows at T = 4 and 6-11% faster at T = 2, 3.
-// FP64: 8 waves of 2 rows.
-template <typename S, int T>
-struct TBConfig {
-    static constexpr int R = 2;
-    static constexpr int W = sizeof(S) == 4 ? 16 : 8;
+// Tile shapes: R rows per thread, W waves per workgroup, PF input planes in
+// flight, and the addressing / prefetch forms (SB, UPF above).  Registers
+// bound them: every level keeps three planes per cell, so a taller tile (less
+// halo per cell) leaves room for fewer planes in flight.  Index 0 is each
+// depth's default, the fastest measured on MI355X for 512^3 FP32 and 256^3
+// FP64 (us per fused launch inside hydro steps, i.e. after the moment and
+// ghost launches):
+//   FP32 T=4: R2 W16 PF3 64-bit 777-782, R2 W16 PF2 SB 804-824,
+//             R3 W16 PF1 SB 883 (the taller tile lacks planes in flight);
+//   FP32 T=3 and T=2: R2 W16 PF3 64-bit 729 and 735 (SB forms 762 and 873
+//             in standalone timing against 735 and 738);
+//   FP64 T=4: R3 W8 PF1 SB 196, R2 W8 PF2 SB 257, R2 W8 PF3 64-bit 289
+//             (a 64 x 24 tile has a 56 x 16 core, against 56 x 8 for 64 x 16);
+//   FP64 T=3 and T=2: R3 W8 PF1 SB 180, R4 W8 PF1 SB 158 (standalone: 200
+//             and 162 against 241 and 174 for R2 W8 PF3 64-bit).
+// The autotuner times every shape of depth 4 (the depth of a 4-substep step).
+struct TileShape {
+    int R, W, PF;
+    bool SB, UPF;
 };
+template <typename S, int T>
+struct TileSet {
+    static constexpr int N = 1;
+    static constexpr TileShape at(int) {
+        return sizeof(S) == 4 ? TileShape{2, 16, 3, false, false}
+                              : (T == 2 ? TileShape{4, 8, 1, true, true} : TileShape{3, 8, 1, true, true});
+    }
+};
+template <typename S>
+struct TileSet<S, 4> {
+    static constexpr int N = 3;
+    static constexpr TileShape at(int i) {
+        return sizeof(S) == 4 ? (i == 1   ? TileShape{2, 16, 2, true, true}
+                                 : i == 2 ? TileShape{3, 16, 1, true, true}
+                                          : TileShape{2, 16, 3, false, false})
+                              : (i == 1   ? TileShape{2, 8, 3, false, false}
+                                 : i == 2 ? TileShape{2, 8, 2, true, true}
+                                          : TileShape{3, 8, 1, true, true});
+    }
+};
+
+inline int tile_count(int T) { return T == 4 ? 3 : 1; }
+
+template <typename S, int T, int I>
+void launch_tblock_shape(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
+                         const StepCoef& c, int ncu, hipStream_t st) {
+    constexpr TileShape sh = TileSet<S, T>::at(I);
+    const TBlockDims d = tblock_dims<T, sh.R, sh.W>(L, ncu);
+    hipLaunchKernelGGL((k_leapfrog_tblock<S, T, sh.R, sh.W, sh.PF, sh.SB, sh.UPF>), dim3(d.nblocks), dim3(64 * sh.W),
+                       0, st, in_n, in_nm1, rho, out_n, out_nm1, L, c, d.zc, d.tiles_x, d.tiles_y);
+}
 
 template <typename S, int T>
 void launch_tblock_t(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
-                     const StepCoef& c, int ncu, hipStream_t st) {
-    constexpr int R = TBConfig<S, T>::R;
-    constexpr int W = TBConfig<S, T>::W;
-    const TBlockDims d = tblock_dims<T, R, W>(L, ncu);
-    hipLaunchKernelGGL((k_leapfrog_tblock<S, T, R, W>), dim3(d.nblocks), dim3(64 * W), 0, st, in_n, in_nm1, rho, out_n,
-                       out_nm1, L, c, d.zc, d.tiles_x, d.tiles_y);
+                     const StepCoef& c, int tile, int ncu, hipStream_t st) {
+    if constexpr (TileSet<S, T>::N > 2) {
+        if (tile == 2) return launch_tblock_shape<S, T, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st);
+    }
+    if constexpr (TileSet<S, T>::N > 1) {
+        if (tile == 1) return launch_tblock_shape<S, T, 1>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st);
+    }
+    launch_tblock_shape<S, T, 0>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st);
 }
 
-// ncu: compute units of the device (one resident workgroup of this kernel each)
+// ncu: compute units of the device (one resident workgroup of this kernel
+// each); tile: index into TileSet<S, T> (a depth with fewer shapes takes 0)
 template <typename S>
 void launch_tblock(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
-                   const StepCoef& c, int T, int ncu, hipStream_t st) {
+                   const StepCoef& c, int T, int tile, int ncu, hipStream_t st) {
     switch (T) {
-        case 2: launch_tblock_t<S, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st); break;
-        case 3: launch_tblock_t<S, 3>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st); break;
-        case 4: launch_tblock_t<S, 4>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st); break;
+        case 2: launch_tblock_t<S, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st); break;
+        case 3: launch_tblock_t<S, 3>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st); break;
+        case 4: launch_tblock_t<S, 4>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st); break;
         default: break;
     }
 }

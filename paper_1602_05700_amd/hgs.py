@@ -77,6 +77,10 @@ _SIGS = {
     "hgs_load_raw": (_i32, [_vp, _vp, _vp, _dbl]),
     "hgs_set_tblock": (_i32, [_vp, _i32]),
     "hgs_get_tblock": (_i32, [_vp]),
+    "hgs_tile_count": (_i32, [_i32]),
+    "hgs_tile_shape": (_i32, [_i32, _i32, _i32, ctypes.POINTER(_i32)]),
+    "hgs_set_tile": (_i32, [_vp, _i32]),
+    "hgs_get_tile": (_i32, [_vp]),
     "hgs_timing_enable": (_i32, [_vp, _i32]),
     "hgs_timing_read": (_i32, [_vp, _i32, _dp]),
     "hgs_workspace_bytes_batch": (_i32, [_CFG, _i32, ctypes.POINTER(_sz)]),
@@ -104,7 +108,8 @@ _SIGS = {
     "hgs_nn_restrict2": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
     "hgs_nn_prolong2": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp]),
     "hgs_nn_last_error": (_cp, []),
-    "hgs_autotune": (_i32, [_CFG, _vp, _dbl, _dbl, _i32, _vp, _sz, ctypes.POINTER(_i32), _dp]),
+    "hgs_autotune": (_i32, [_CFG, _vp, _dbl, _dbl, _i32, _vp, _sz, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                            _dp]),
     "hgs_destroy": (_i32, [_vp]),
     "hgs_status_str": (_cp, [_i32]),
     "hgs_last_error": (_cp, [_vp]),
@@ -167,7 +172,7 @@ class Solver:
 
     def __init__(self, shape, x0=(-1.0, -1.0, -1.0), dx: Optional[float] = None, G: float = 1.0,
                  origin=(0.0, 0.0, 0.0), lmax: int = 4, bc: str = "multipole", storage: str = "f32",
-                 tblock: int = 0, eta: float = 0.0, device="cuda", stream=None):
+                 tblock: int = 0, eta: float = 0.0, device="cuda", stream=None, tile: int = 0):
         import torch
 
         self.torch = torch
@@ -185,6 +190,8 @@ class Solver:
         _check(_lib.hgs_init(ctypes.byref(self.cfg), self.workspace.data_ptr(), nbytes, ctypes.byref(h)))
         self._h = h
         self._owned = True
+        if tile:
+            self.set_tile(tile)
 
     @classmethod
     def _view(cls, handle, cfg, device, dtype, stream, owner):
@@ -345,6 +352,13 @@ class Solver:
     @property
     def tblock(self) -> int:
         return int(_lib.hgs_get_tblock(self._h))
+
+    def set_tile(self, tile: int) -> None:
+        _check(_lib.hgs_set_tile(self._h, int(tile)), self._h)
+
+    @property
+    def tile(self) -> int:
+        return int(_lib.hgs_get_tile(self._h))
 
     def close(self) -> None:
         if getattr(self, "_h", None) and getattr(self, "_owned", True):
@@ -518,11 +532,24 @@ class NestedSolver:
             s.close()
 
 
+def tile_count(tblock: int) -> int:
+    """Tile shapes compiled for fused depth tblock."""
+    return int(_lib.hgs_tile_count(int(tblock)))
+
+
+def tile_shape(storage: str, tblock: int, tile: int):
+    """(rows per thread, waves per workgroup, input planes in flight) of a tile."""
+    sh = (_i32 * 3)()
+    _check(_lib.hgs_tile_shape(HGS_F64 if storage == "f64" else HGS_F32, int(tblock), int(tile), sh))
+    return tuple(int(v) for v in sh)
+
+
 def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32", lmax: int = 4,
              x0=(-1.0, -1.0, -1.0), dx=None, eta: float = 0.0, bc: str = "multipole", device="cuda", stream=None):
-    """Fastest fused depth for hydro steps of nsub substeps on this grid (the
-    library times every depth on a temporary workspace).  Returns
-    (best_tblock, [ms per substep for depth 1..TMAX] or None when cached)."""
+    """Fastest fused depth and tile shape for hydro steps of nsub substeps on
+    this grid (the library times every depth and every tile compiled for it
+    on a temporary workspace).  Returns (best_tblock, best_tile, [best ms per
+    substep for depth 1..TMAX] or None when cached)."""
     import torch
 
     dev = torch.device(device)
@@ -531,11 +558,12 @@ def autotune(shape, rho, c_g: float, dt: float, nsub: int, storage: str = "f32",
     nb = workspace_bytes(cfg)
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     best = _i32(0)
+    tile = _i32(0)
     ms = (ctypes.c_double * TMAX)()
     _check(_lib.hgs_autotune(ctypes.byref(cfg), rho.data_ptr(), float(c_g), float(dt), int(nsub), ws.data_ptr(), nb,
-                             ctypes.byref(best), ms))
+                             ctypes.byref(best), ctypes.byref(tile), ms))
     times = list(ms)
-    return int(best.value), (None if times[0] < 0 else times)
+    return int(best.value), int(tile.value), (None if times[0] < 0 else times)
 
 
 class Batch:

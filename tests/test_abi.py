@@ -31,7 +31,7 @@ def test_binding_covers_the_header():
 
 def test_abi_version_and_status_strings():
     L = hgs.library()
-    assert L.hgs_abi_version() == 1
+    assert L.hgs_abi_version() == 2
     assert L.hgs_status_str(hgs.HGS_ERR_CFL) == b"HGS_ERR_CFL"
     assert L.hgs_status_str(99) == b"HGS_ERR_UNKNOWN"
 

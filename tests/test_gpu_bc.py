@@ -145,9 +145,9 @@ def test_local_bc_rejected_in_batch_and_tuned_to_one(gpu_lib):
     with pytest.raises(hgs.HGSError):
         hgs.Batch([16, 32], bc="robin", storage="f32", device="cuda")
     rho = to_dev(dens((16, 16, 16), 27, "f32"))
-    best, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc="periodic",
-                               device="cuda")
-    assert best == 1
+    best, tile, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc="periodic",
+                                     device="cuda")
+    assert best == 1 and tile == 0
 
 
 def test_periodic_and_energy_256_against_oracle(gpu_lib):

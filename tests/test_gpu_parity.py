@@ -492,11 +492,52 @@ def test_tblock_bitwise_equals_streaming(gpu_lib, storage, shape, T):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_tblock_against_oracle(gpu_lib, storage):
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 3, 7), (23, 29, 37), (40, 33, 130), (70, 61, 66), (9, 150, 67)])
+@pytest.mark.parametrize("tile", [1, 2])
+def test_tile_shapes_bitwise_equal(gpu_lib, storage, shape, tile):
+    """Every tile shape compiled for the depth-4 fused launch gives the
+    default shape's results bit for bit (taller tiles, fewer planes in flight:
+    the same levels in the same rounding), on grids with ragged tiles in every
+    direction and more tiles in y than the default shape needs."""
+    import torch
+
+    assert gpu_lib.tile_count(4) == 3
+    rt, wt, pft = gpu_lib.tile_shape(storage, 4, tile)
+    r0, w0, pf0 = gpu_lib.tile_shape(storage, 4, 0)
+    assert (rt, wt, pft) != (r0, w0, pf0)
+    g = grid_of(shape)
+    rho = to_dev(dens(shape, 14, storage))
+    a = solver(gpu_lib, shape, storage=storage, eta=0.7, tblock=4)
+    b = solver(gpu_lib, shape, storage=storage, eta=0.7, tblock=4, tile=tile)
+    assert a.tile == 0 and b.tile == tile
+    for dt, nsub in [(0.4, 4), (0.4, 9), (0.3, 8)]:
+        a.step(rho, 1.0, dt * g.dx, nsub)
+        b.step(rho, 1.0, dt * g.dx, nsub)
+    ra, rb = a.save_raw(), b.save_raw()
+    torch.cuda.synchronize()
+    assert torch.equal(ra[0], rb[0]) and torch.equal(ra[1], rb[1])
+
+
+def test_tile_api_validates(gpu_lib):
+    with pytest.raises(gpu_lib.HGSError):
+        gpu_lib.tile_shape("f32", 4, 3)
+    with pytest.raises(gpu_lib.HGSError):
+        gpu_lib.tile_shape("f32", 1, 0)
+    assert gpu_lib.tile_count(1) == 0 and gpu_lib.tile_count(2) == 1
+    s = solver(gpu_lib, (8, 8, 8), storage="f32")
+    with pytest.raises(gpu_lib.HGSError):
+        s.set_tile(3)
+    assert s.tile == 0
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("tile", [0, 1])
+def test_tblock_against_oracle(gpu_lib, storage, tile):
     shape = (48, 52, 70)
     g = grid_of(shape)
     rho = dens(shape, 13, storage)
     s, o = pair(gpu_lib, shape, storage, eta=0.0, tblock=4)
+    s.set_tile(tile)
     for _ in range(5):
         s.step(to_dev(rho), 1.0, 0.4 * g.dx, 4)
         o.step(rho.astype(np.float64), 1.0, 0.4 * g.dx, 4)
@@ -589,15 +630,20 @@ def test_autotune_and_cache(gpu_lib, tmp_path, monkeypatch):
     g = grid_of(shape)
     rho = to_dev(dens(shape, 3, "f32"))
     monkeypatch.delenv("HGS_TUNE_CACHE", raising=False)
-    best, times = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
+    best, tile, times = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
     assert 1 <= best <= gpu_lib.TMAX and times is not None and len(times) == gpu_lib.TMAX
     assert all(t > 0 for t in times) and times[best - 1] == min(times)
+    assert 0 <= tile < max(1, gpu_lib.tile_count(best))
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("HGS_TUNE_CACHE", str(cache))
-    b1, t1 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
+    b1, k1, t1 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
     assert t1 is not None and cache.exists()
-    b2, t2 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
-    assert b2 == b1 and t2 is None  # served from the cache
+    b2, k2, t2 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
+    assert (b2, k2) == (b1, k1) and t2 is None  # served from the cache
+    # an entry written before tiles were cached (no tile field) reads as tile 0
+    key = cache.read_text().splitlines()[-1].rsplit(" ", 2)[0]
+    cache.write_text(f"{key} 3\n")
+    assert gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)[:2] == (3, 0)
 
 
 def test_fp32_storage_keeps_fp64_accuracy_at_convergence(gpu_lib):
