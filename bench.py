@@ -206,9 +206,10 @@ def run_configs(dev):
     rho = torch.from_numpy(workloads.sphere_density(n, 0.25)).to(dev)
     lam = 3 * (4 / dx ** 2) * math.sin(math.pi / (2 * (n + 1))) ** 2  # slowest Dirichlet mode
     for label, eta in (("eta_0", 0.0), ("eta_critical", 2.0 * math.sqrt(lam))):
-        # fused depth by the library's autotuner (timed on 8-substep steps):
+        # fused depth and tile by the library's autotuner (timed on 200-substep
+        # steps, so the per-step moment and ghost launches weigh as in the run):
         # at 64^3 a fused launch is bound by its pipeline fill, not by HBM
-        tb, tile, _ = hgs.autotune(n, rho, 1.0, dt, 8, storage="f64", lmax=0, eta=eta, device=dev)
+        tb, tile, _ = hgs.autotune(n, rho, 1.0, dt, 200, storage="f64", lmax=0, eta=eta, device=dev)
         s = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, tile=tile, device=dev)
         s.step(rho, 1.0, dt, 8)  # warm-up
         s2 = hgs.Solver(n, storage="f64", lmax=0, eta=eta, tblock=tb, tile=tile, device=dev)
@@ -258,8 +259,79 @@ def run_configs(dev):
         s.close()
         del rhos, g
         torch.cuda.empty_cache()
+    out["tracking_256"] = run_tracking(dev)
     out["next_rows_256_f32"] = run_next_rows(dev)
     return out
+
+
+def run_tracking(dev, n=256, nsub=4, steps=250, every=5, omega=0.1):
+    """Tracking accuracy of the 256^3 rotating configuration (8 blobs, seed 0,
+    speed 0.1 c_g at radius 1, l <= 4, 4 substeps per hydro step, eta = 0)
+    over 250 hydro steps from the converged potential of the first density
+    with the rigid-rotation phidot, in FP64 and FP32 storage: the paper's
+    average relative error (Eq. 6, the volume RMS of (phi_H - phi_P) / phi_P,
+    Eq. 5) against the Poisson solution phi_P of the density of the last hydro
+    step, every `every` hydro steps.  phi_P is the solver's own damped
+    relaxation (FP64, critical damping) carried from checkpoint to checkpoint:
+    the damped iteration's fixed point is the discrete Poisson solution, and
+    its residual R_b is reported with the errors."""
+    import math
+
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import hgs
+
+    dx = 2.0 / n
+    dt = 0.4 * dx
+    lam = 3 * (4 / dx ** 2) * math.sin(math.pi / (2 * (n + 1))) ** 2
+    eta_c = 2.0 * math.sqrt(lam)
+    blobs = workloads.blob_params(0, 8)
+    dens = lambda h, tdt: workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * h), dev, tdt)
+    ref = hgs.Solver(n, storage="f64", lmax=4, eta=eta_c, device=dev)
+    r0 = dens(0, torch.float64)
+    ref.step(r0, 1.0, dt, 4000)
+    start_rb = float(ref.residual(r0)[0])
+    phi0 = ref.potential(with_phidot=False)[0]
+    ax = -1.0 + (torch.arange(n, device=dev, dtype=torch.float64) + 0.5) * dx
+    dpy, dpx = torch.gradient(phi0, spacing=dx, dim=(1, 2))
+    pd0 = (-omega * (ax[None, None, :] * dpy - ax[None, :, None] * dpx)).contiguous()
+    del dpy, dpx
+    runs = {}
+    for storage, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        s = hgs.Solver(n, storage=storage, lmax=4, eta=0.0, device=dev)
+        s.set_state(phi0.to(tdt), pd0.to(tdt), dt)
+        runs[storage] = s
+    eq6 = {"f64": [], "f32": []}
+    ref_rb = []
+    t0 = time.time()
+    for h in range(1, steps + 1):
+        rho64 = dens(h - 1, torch.float64)
+        runs["f64"].step(rho64, 1.0, dt, nsub)
+        runs["f32"].step(rho64.float(), 1.0, dt, nsub)
+        if h % every == 0:
+            ref.step(rho64, 1.0, dt, 1600)  # relax the Poisson reference to this density
+            ref_rb.append(float(ref.residual(rho64)[0]))
+            phi_p = ref.potential(with_phidot=False)[0]
+            for storage, sv in runs.items():
+                d = (sv.potential(with_phidot=False)[0].double() - phi_p) / phi_p
+                eq6[storage].append(float(torch.sqrt(torch.mean(d * d))))
+    fin = {k: v.potential(with_phidot=False)[0].double() for k, v in runs.items()}
+    diff = float((fin["f32"] - fin["f64"]).abs().max() / fin["f64"].abs().max())
+    for v in runs.values():
+        v.close()
+    ref.close()
+    log(f"[bench] tracking 256^3: {steps} hydro steps in {time.time() - t0:.1f} s, "
+        f"Eq. 6 max f64 {max(eq6['f64']):.3e} f32 {max(eq6['f32']):.3e}")
+    return {"hydro_steps": steps, "every": every, "metric": "Eq. 6 (volume RMS of (phi_H - phi_P)/phi_P)",
+            "reference": "FP64 damped relaxation, 1600 critically damped substeps per checkpoint",
+            "start_R_b": start_rb, "reference_R_b_max": max(ref_rb),
+            "eq6_f64": {"max": max(eq6["f64"]), "final": eq6["f64"][-1], "mean": sum(eq6["f64"]) / len(eq6["f64"])},
+            "eq6_f32": {"max": max(eq6["f32"]), "final": eq6["f32"][-1], "mean": sum(eq6["f32"]) / len(eq6["f32"])},
+            "eq6_at": {str(h): [round(a, 8), round(b, 8)] for h, a, b in
+                       zip(range(every, steps + 1, every), eq6["f64"], eq6["f32"])
+                       if h in (every, 25, 50, 100, 150, 200, steps)},
+            "f32_vs_f64_phi_maxrel_final": diff}
 
 
 def run_next_rows(dev, n=256, nsub=4, steps=20):

@@ -338,17 +338,21 @@ inline TBlockDims tblock_dims(const Layout& L, int slots) {
 //             (a 64 x 24 tile has a 56 x 16 core, against 56 x 8 for 64 x 16);
 //   FP64 T=3 and T=2: R3 W8 PF1 SB 180, R4 W8 PF1 SB 158 (standalone: 200
 //             and 162 against 241 and 174 for R2 W8 PF3 64-bit).
-// The autotuner times every shape of depth 4 (the depth of a 4-substep step).
+// The autotuner times every shape of every depth.
 struct TileShape {
     int R, W, PF;
     bool SB, UPF;
 };
 template <typename S, int T>
 struct TileSet {
-    static constexpr int N = 1;
-    static constexpr TileShape at(int) {
-        return sizeof(S) == 4 ? TileShape{2, 16, 3, false, false}
-                              : (T == 2 ? TileShape{4, 8, 1, true, true} : TileShape{3, 8, 1, true, true});
+    static constexpr int N = 2;
+    static constexpr TileShape at(int i) {
+        // the second shape of depths 2 and 3 is the other family: the taller
+        // tile for FP32, the shorter one for FP64 (more tiles for small grids)
+        return sizeof(S) == 4 ? (i == 1 ? (T == 2 ? TileShape{4, 16, 2, true, true} : TileShape{3, 16, 2, true, true})
+                                        : TileShape{2, 16, 3, false, false})
+                              : (i == 1 ? TileShape{2, 8, 3, false, false}
+                                        : (T == 2 ? TileShape{4, 8, 1, true, true} : TileShape{3, 8, 1, true, true}));
     }
 };
 template <typename S>
@@ -364,7 +368,7 @@ struct TileSet<S, 4> {
     }
 };
 
-inline int tile_count(int T) { return T == 4 ? 3 : 1; }
+inline int tile_count(int T) { return T == 4 ? 3 : (T >= 2 ? 2 : 1); }
 
 template <typename S, int T, int I>
 void launch_tblock_shape(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,

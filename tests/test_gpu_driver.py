@@ -110,10 +110,27 @@ def _poisson(g, rho):
     return poisson.solve_dst(g, rho, 1.0, P)
 
 
-def _h_vs_p_error(hgs, k_g, n=32, omega=0.5, ch=0.075, steps=240):
-    """Mean relative difference <|phi_H - phi_P|> / <|phi_P|> over the last
-    third of a run in which a blob mixture rotates rigidly about z, coupled
-    through hgs_hydro_step (multipole boundary, eta = 0, c_s = 0)."""
+def _h_vs_p_error(hgs, k_g, n=32, omega=0.5, ch=0.01875, courant_grav=0.3, t_total=1.64):
+    """The paper's average relative error (Eq. 6) of the hyperbolic potential
+    phi_H against the Poisson solution phi_P of the current density, averaged
+    over the last third of a run in which a blob mixture rotates rigidly about
+    z (multipole boundary, eta = 0, c_s = 0), coupled as the driver does it:
+    c_g = k_g max(c_s + |v|) from the GPU's signal-speed reduction and
+    nsub = 2 ceil(k_g C_h / (2 C_g)) substeps of dt_h / nsub per hydro step
+    with the density frozen at the step's mid-time.
+
+    The measurement isolates the error of Eq. 7 (the wave equation's lag
+    behind the moving source, Eq. 12):
+      * it starts from the Poisson solution with phidot the time derivative of
+        the discrete Poisson solution along the rotation (central difference
+        in time of two DST-I solves), so the start injects no free wave;
+      * each hydro step is taken as two halves and phi_H is sampled at the
+        mid-time, where the frozen density equals the density at that time
+        (sampling at the step's end would compare against a density half a
+        step away: an error first order in dt_h, independent of k_g);
+      * dt_h is small (Courant number 0.01875 for the flow): the jump of the
+        frozen density between steps kicks the modes that react within a
+        hydro step, a floor first order in dt_h that grows with k_g."""
     import torch
 
     shape = (n, n, n)
@@ -125,47 +142,46 @@ def _h_vs_p_error(hgs, k_g, n=32, omega=0.5, ch=0.075, steps=240):
     vx, vy = to_dev(-omega * Y), to_dev(omega * X)
     vz = torch.zeros_like(vx)
     cs = torch.zeros_like(vx)
-    vmax = omega * float(np.sqrt(X ** 2 + Y ** 2).max())
-    # start: the Poisson solution and the time derivative of rigid rotation,
-    # d phi / dt = -omega (x d/dy - y d/dx) phi
     phi0 = _poisson(g, rho_at(0.0))
-    Pf = padded(g)
-    interior(Pf)[...] = phi0
-    q = core.moments(g, rho_at(0.0), 4)
-    core.boundary(g, q, 4, 1.0, Pf)
-    dpx = (Pf[1:-1, 1:-1, 2:] - Pf[1:-1, 1:-1, :-2]) / (2 * g.dx)
-    dpy = (Pf[1:-1, 2:, 1:-1] - Pf[1:-1, :-2, 1:-1]) / (2 * g.dx)
-    pd0 = -omega * (X * dpy - Y * dpx)
+    d = 1e-4
+    pd0 = (_poisson(g, rho_at(d)) - _poisson(g, rho_at(-d))) / (2 * d)
     s = solver(hgs, shape, storage="f64")
+    vmax = s.max_signal_speed(cs, (vx, vy, vz))
+    assert vmax == pytest.approx(omega * float(np.sqrt(X ** 2 + Y ** 2).max()), rel=1e-14)
+    c_g = k_g * vmax
     dth = ch * g.dx / vmax
-    nsub = math.ceil(k_g * ch / 0.3 - 1e-9)
+    half = math.ceil(k_g * ch / (2 * courant_grav) - 1e-9)
+    nsub = 2 * half
     s.set_state(to_dev(phi0), to_dev(pd0), dth / nsub)
+    steps = int(round(t_total / dth))
     errs, t = [], 0.0
     for h in range(steps):
         rho = rho_at(t + 0.5 * dth)  # frozen over the hydrodynamical step
-        dt_h, _, _ = s.hydro_step(to_dev(rho), cs, (vx, vy, vz), k_g=k_g, courant_hydro=ch, courant_grav=0.3)
-        t += dt_h
+        rd = to_dev(rho)
+        s.step(rd, c_g, dth / nsub, half)
         if h >= steps - steps // 3 and h % (steps // 15) == 0:
-            ref = _poisson(g, rho)
-            errs.append(np.mean(np.abs(host(s.potential()[0]) - ref)) / np.mean(np.abs(ref)))
+            errs.append(poisson.mean_relative_error(host(s.potential()[0]), _poisson(g, rho)))
+        s.step(rd, c_g, dth / nsub, half)
+        t += dth
     return float(np.mean(errs)), vmax
 
 
 def test_error_estimate_eq12(gpu_lib):
-    """The difference from the Poisson solution falls with k_g toward a floor
-    set by the frozen density (first order in dt_hydro, independent of k_g).
-    Above that floor (taken as the k_g = 16 value) it falls from k_g = 2 to 4
-    by more than a first-order term in v / c_g allows, (1/2 - 1/16) /
-    (1/4 - 1/16) = 2.33; second order, as Eq. 12 estimates, gives 4.2.  All stay
-    below (v_max / c_g)^2 = 1 / k_g^2."""
+    """Eq. 12: the relative error of the hyperbolic potential against the
+    Poisson solution is of order (c_s^2 + v^2) / c_g^2, second order in
+    1 / k_g.  Fitting log(error) against log(k_g) over k_g = 2, 4, 8 gives an
+    exponent in [1.6, 2.4] (a first-order error would give 1), and every error
+    stays below (v_max / c_g)^2 = 1 / k_g^2.  The CPU oracle with the same
+    protocol gives 2.70e-3, 7.64e-4, 1.80e-4 (exponent 1.96)."""
     errs = {}
-    for k_g in (2.0, 4.0, 8.0, 16.0):
+    for k_g in (2.0, 4.0, 8.0):
         errs[k_g], vmax = _h_vs_p_error(gpu_lib, k_g)
     ks = sorted(errs)
+    slope = float(np.polyfit(np.log(ks), np.log([errs[k] for k in ks]), 1)[0])
+    print({k: f"{v:.3e}" for k, v in errs.items()}, f"exponent {-slope:.3f}")
+    assert 1.6 <= -slope <= 2.4, (slope, errs)
     for a, b in zip(ks, ks[1:]):
-        assert errs[b] <= errs[a] * 1.05, errs
-    floor = errs[16.0]
-    assert (errs[2.0] - floor) / (errs[4.0] - floor) > 2.8, errs
+        assert errs[b] < errs[a], errs
     for k in ks:
         assert errs[k] < 1.0 / k ** 2, errs
 
@@ -176,10 +192,10 @@ def test_tracking_256_rotating_eq6():
     """The 256^3 rotating configuration (8 blobs, seed 0, speed 0.1 c_g at
     radius 1, centres turned before each hydro step, lmax 4, 4 substeps per
     hydro step, eta = 0) started from the Poisson solution with the time
-    derivative of rigid rotation: the paper's average relative error (Eq. 6)
-    against the Poisson solution of the current density stays below 1e-2
-    (it scales as (v / c_g)^2, Eq. 12) in FP64 and FP32 storage, and the two
-    storages agree far below that."""
+    derivative of rigid rotation, over 250 hydro steps: the paper's average
+    relative error (Eq. 6) against the Poisson solution (oracle DST-I) of the
+    current density stays below 1e-2 (it scales as (v / c_g)^2, Eq. 12) in
+    FP64 and FP32 storage, and the two storages agree far below that."""
     import torch
 
     from paper_1602_05700_amd import hgs
@@ -200,7 +216,7 @@ def test_tracking_256_rotating_eq6():
     Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
     pd0 = -omega * (X * dpy - Y * dpx)
     del Pf, dpx, dpy, Z, Y, X
-    checks = (10, 30, 60)
+    checks = (10, 60, 250)
     refs = {h: _poisson(g, rho_h(h - 1)) for h in checks}  # the density of the last step taken
     errs = {}
     finals = {}
