@@ -65,16 +65,18 @@ def kernel_source_hash(kernel: str = "leapfrog_tblock") -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel: str, launches_cells: int):
+def counter_traffic(kernel: str, launches_cells: int, tile: int = 0):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources and workload; else None."""
+    was taken on the current kernel sources, workload and tile shape; else
+    None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
         e = d.get(kernel)
-        if not e or e.get("source_hash") != kernel_source_hash(kernel) or e.get("cells") != launches_cells:
+        if (not e or e.get("source_hash") != kernel_source_hash(kernel) or e.get("cells") != launches_cells
+                or e.get("tile", 0) != tile):
             return None
         return float(e["bytes_per_launch"])
     except Exception:
@@ -147,7 +149,9 @@ def run_batched(dev, nsub=500, seed=2, count=64):
     """64 independent cube grids, N in {32, 48, ..., 160} drawn with the seed,
     each with its own 4-12 blob density, FP32 storage, lmax 4; one hydro step
     of 500 substeps (dt = 0.4 dx_g) for all grids together, replayed from a
-    captured graph.  Returns total cell updates per second."""
+    captured graph.  Returns total cell updates per second of the default
+    launch form (one workgroup per work item, grid-ordered), and the
+    persistent form's beside it."""
     import torch
 
     import workloads
@@ -158,17 +162,22 @@ def run_batched(dev, nsub=500, seed=2, count=64):
             for n, k, s in zip(spec.sizes, spec.nblobs, spec.seeds)]
     b = hgs.Batch(list(spec.sizes), storage="f32", lmax=4, eta=0.0, device=dev)
     dts = [0.4 * 2.0 / n for n in spec.sizes]
-    b.step(rhos, 1.0, dts, nsub)  # warm-up: captures the graph
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    reps = 2
-    e0.record(b.stream)
-    for _ in range(reps):
-        b.step(rhos, 1.0, dts, nsub)
-    e1.record(b.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def timed(launch, reps=2):
+        b.set_launch(launch)
+        b.step(rhos, 1.0, dts, nsub)  # warm-up: captures the graph of this launch form
+        torch.cuda.synchronize()
+        e0.record(b.stream)
+        for _ in range(reps):
+            b.step(rhos, 1.0, dts, nsub)
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_persistent = timed("persistent")
+    ms = timed("per_item")  # the default launch form, timed last
     cells = sum(n ** 3 for n in spec.sizes)
     T = b.grids[0].tblock
     # algorithmic bytes of the substeps: per fused launch each cell's phi^n,
@@ -180,8 +189,10 @@ def run_batched(dev, nsub=500, seed=2, count=64):
     gbps = stencil_bytes / (ms / 1e3) / 1e9
     return {"grids": count, "cells": cells, "substeps": nsub, "ms_per_hydro_step": round(ms, 3),
             "value": round(cells * nsub / (ms / 1e3) / 1e9, 3), "unit": "Gcell-updates/s",
-            "graph": b.used_graph, "tblock": T, "stencil_GBps_algorithmic": round(gbps, 1),
-            "hbm_frac": round(gbps / PEAK_HBM_GBS, 4)}
+            "graph": b.used_graph, "tblock": T, "launch": b.launch, "stencil_GBps_algorithmic": round(gbps, 1),
+            "hbm_frac": round(gbps / PEAK_HBM_GBS, 4),
+            "persistent_launch": {"ms_per_hydro_step": round(ms_persistent, 3),
+                                  "value": round(cells * nsub / (ms_persistent / 1e3) / 1e9, 3)}}
 
 
 def run_configs(dev):
@@ -490,11 +501,13 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
     """Substeps of the critically damped FP32 solver to R_b < tol on 128^3
     blob mixtures (held-out seeds 20000..), from the zero start and from the
     learned start with the committed weights (zero start as fallback); the
-    coarse solve that feeds the network is counted in fine-substep
-    equivalents.  Wall time as well: one density's prediction (restriction,
-    coarse solve, features, network, prolongation) plus the median learned
-    substep count, against the median zero-start count, each timed with events
-    as one uninterrupted sequence of launches."""
+    coarse cue that feeds the network (the direct Poisson solve on the n/4
+    grid) is counted in fine-substep equivalents.  Wall time as well: one
+    density's prediction (restriction, coarse solve, features, network,
+    prolongation; replayed from a captured graph), the fallback check
+    (start_solver: ghosts, residual, the decision on the device) and the median learned
+    substep count, against the median zero-start count, each timed with
+    events from the first launch to the last."""
     import numpy as np
     import torch
 
@@ -513,13 +526,12 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
     zero, learned, fallback = [], [], 0
     for i in range(count):
         z = ws.steps_to_tolerance(rho[i], n, tol)
+        # the start goes through start_solver: on a fallback the substeps are
+        # counted from the zero start, and the prediction is counted either way
         w = ws.steps_to_tolerance(rho[i], n, tol, start=(phi[i], pd[i]))
         zero.append(z[0])
-        if w[1] >= z[1]:
-            fallback += 1
-            learned.append(z[0] + 4)
-        else:
-            learned.append(w[0] + feats.coarse_cost_fine_steps)
+        fallback += 0 if w[3] else 1
+        learned.append(w[0] + feats.coarse_cost_fine_steps)
     mz, ml = float(np.median(zero)), float(np.median(learned))
 
     # wall time, density 0: prediction for one density, then the substeps
@@ -535,21 +547,25 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
             s.set_state(start[0], start[1], dt)
         return s
 
-    for rep in range(2):  # first pass warms up
+    n_l = int(round(np.median([v - feats.coarse_cost_fine_steps for v in learned])))
+    predictor = ws.Predictor(net, n, B=1, device=dev)  # the prediction captured in a graph
+    for rep in range(3):  # the first passes warm up
+        s = solve(None, 0)  # created outside the timed region, as for the zero start
         torch.cuda.synchronize()
         e[0].record()
-        p_in, p_c, p_s = feats.inputs(r0[None])
-        f_phi, f_pd = ws.predict_fine(net, p_in, p_c, p_s, n)
+        f_phi, f_pd = predictor(r0[None])
         e[1].record()
-        s = solve((f_phi[0].contiguous(), f_pd[0].contiguous()), 0)
-        n_l = int(round(np.median([v - feats.coarse_cost_fine_steps for v in learned])))
+        # the fallback check (ghosts, residual, the decision on the device) is timed too
+        kept = ws.start_solver(s, r0, f_phi[0].contiguous(), f_pd[0].contiguous(), dt)
         e[2].record()
         s.step(r0, 1.0, dt, n_l)
         e[3].record()
         torch.cuda.synchronize()
+        assert kept.item() == 1, "the timed density fell back to the zero start"
         s.close()
     predict_ms = e[0].elapsed_time(e[1])
-    learned_ms = predict_ms + e[2].elapsed_time(e[3])
+    check_ms = e[1].elapsed_time(e[2])
+    learned_ms = e[0].elapsed_time(e[3])
     s = solve(None, 0)
     torch.cuda.synchronize()
     e[0].record()
@@ -560,9 +576,10 @@ def run_warmstart(dev, count=8, n=128, tol=1e-4):
     s.close()
     return {"grid": n, "densities": count, "seeds": f"{seeds[0]}..{seeds[-1]}", "tol_Rb": tol,
             "steps_zero_median": mz, "steps_learned_median": round(ml, 2), "ratio": round(mz / ml, 3),
-            "fallback": fallback, "coarse_cost_fine_steps": feats.coarse_cost_fine_steps,
+            "fallback": fallback, "coarse_cue": feats.coarse, "coarse_cost_fine_steps": feats.coarse_cost_fine_steps,
             "wall_ms_zero": round(zero_ms, 3), "wall_ms_learned": round(learned_ms, 3),
-            "wall_ms_predict": round(predict_ms, 3), "wall_ratio": round(zero_ms / learned_ms, 3)}
+            "wall_ms_predict": round(predict_ms, 3), "wall_ms_fallback_check": round(check_ms, 3),
+            "wall_ratio": round(zero_ms / learned_ms, 3)}
 
 
 def main():
@@ -574,6 +591,8 @@ def main():
     ap.add_argument("--nsub", type=int, default=4)
     ap.add_argument("--tblock", type=int, default=0, help="substeps per fused launch (0 = autotune)")
     ap.add_argument("--tile", type=int, default=0, help="tile shape index with --tblock (hgs_tile_shape)")
+    ap.add_argument("--storage", choices=("f32", "f64"), default="f32",
+                    help="storage of the headline run (f32: the headline configuration; f64 for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched measurement")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the steps-to-1e-4 warm-start measurement")
@@ -611,30 +630,32 @@ def main():
     dt = 0.4 * dx / c_g
     omega = 0.1 * c_g / 1.0  # speed 0.1 c_g at cylindrical radius 1
     blobs = workloads.blob_params(1, 16)
-    log(f"[bench] generating {W + K} rotated densities {n}^3 fp32 on the GPU")
-    rhos = [workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * h), dev, torch.float32)
+    storage = args.storage
+    tdt = torch.float32 if storage == "f32" else torch.float64
+    log(f"[bench] generating {W + K} rotated densities {n}^3 {storage} on the GPU")
+    rhos = [workloads.blob_density_torch(n, blobs.rotated(omega * nsub * dt * h), dev, tdt)
             for h in range(W + K)]
     tune = None
     tblock, tile = args.tblock, args.tile
     if tblock == 0:
-        best, best_tile, times = hgs.autotune(n, rhos[0], c_g, dt, nsub, storage="f32", lmax=4, device=dev)
-        tune = {"best_tblock": best, "best_tile": tile_desc("f32", best, best_tile), "ms_per_substep": times}
+        best, best_tile, times = hgs.autotune(n, rhos[0], c_g, dt, nsub, storage=storage, lmax=4, device=dev)
+        tune = {"best_tblock": best, "best_tile": tile_desc(storage, best, best_tile), "ms_per_substep": times}
         tblock, tile = best, best_tile
         log(f"[bench] autotune: depth {best}, tile {tune['best_tile']}, ms per substep {times}")
-    s = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, tblock=tblock, tile=tile, device=dev)
-    out = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in range(3)]
+    s = hgs.Solver(n, storage=storage, lmax=4, eta=0.0, tblock=tblock, tile=tile, device=dev)
+    out = [torch.empty((n, n, n), dtype=tdt, device=dev) for _ in range(3)]
     stream = s.stream
     # start: the converged potential of the first density (critically damped
     # relaxation) and the time derivative of rigid rotation about z,
     # dphi/dt = -omega (x d/dy - y d/dx) phi; then the undamped Eq. (2)
     log(f"[bench] converged start: {CONVERGE_SUBSTEPS} critically damped substeps")
     lam = 3 * (4 / dx ** 2) * math.sin(math.pi / (2 * (n + 1))) ** 2
-    sc = hgs.Solver(n, storage="f32", lmax=4, eta=2.0 * c_g * math.sqrt(lam), device=dev)
+    sc = hgs.Solver(n, storage=storage, lmax=4, eta=2.0 * c_g * math.sqrt(lam), device=dev)
     sc.step(rhos[0], c_g, dt, CONVERGE_SUBSTEPS)
     start_res = sc.residual(rhos[0])
     phi_c = sc.potential(with_phidot=False)[0]
     sc.close()
-    ax = -1.0 + (torch.arange(n, device=dev, dtype=torch.float32) + 0.5) * dx
+    ax = -1.0 + (torch.arange(n, device=dev, dtype=tdt) + 0.5) * dx
     dpy, dpx = torch.gradient(phi_c, spacing=dx, dim=(1, 2))
     pd0 = -omega * (ax[None, None, :] * dpy - ax[None, :, None] * dpx)
     s.set_state(phi_c, pd0.contiguous(), dt)
@@ -675,8 +696,8 @@ def main():
     per_launch_bytes = st["bytes"] / st["launches"]
     avg_s = st["ms"] / st["launches"] / 1e3
     achieved = per_launch_bytes / avg_s / 1e9
-    kname = "leapfrog_stream" if s.tblock == 1 else f"leapfrog_tblock{s.tblock}"
-    traffic = counter_traffic(kname, n ** 3)
+    kname = ("leapfrog_stream" if s.tblock == 1 else f"leapfrog_tblock{s.tblock}") + ("_f64" if storage == "f64" else "")
+    traffic = counter_traffic(kname, n ** 3, s.tile if s.tblock > 1 else 0)
     line = {
         "metric": "Gcell-updates/s + %HBM roofline; steps to 1e-4 residual, plain vs learned",
         "value": round(value, 3),
@@ -688,13 +709,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (storage and substeps; f64 moments, boundary and gradient)",
+        "dtype": ("f32 (storage and substeps; f64 moments, boundary and gradient)" if storage == "f32"
+                  else "f64"),
         "data": "synthetic",
         "config": {
-            "workload": f"hyperbolic gravity, {n}^3 grid, 16 rotating Gaussian blobs, FP32 storage, lmax 4, "
+            "workload": f"hyperbolic gravity, {n}^3 grid, 16 rotating Gaussian blobs, {storage.upper()} storage, lmax 4, "
                         f"{nsub} substeps per hydro step, moments+ghosts+substeps+gradient, from the converged "
                         "potential with the rotation's time derivative",
-            "grid": n, "nsub": nsub, "tblock": s.tblock, "tile": tile_desc("f32", s.tblock, s.tile), "lmax": 4,
+            "grid": n, "nsub": nsub, "tblock": s.tblock, "tile": tile_desc(storage, s.tblock, s.tile), "lmax": 4,
             "blobs": 16,
         },
         "roofline": {

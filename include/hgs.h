@@ -142,6 +142,40 @@ hgs_status hgs_step(hgs_ctx* ctx, const void* rho, double c_g, double dt, int32_
  * finite; HGS_ERR_CFL when c_g dt / dx > 1/sqrt(3); else HGS_OK. */
 hgs_status hgs_validate_step(const hgs_config* cfg, const void* rho, double c_g, double dt, int32_t nsub);
 
+/* bc = MULTIPOLE: the first stage of hgs_step alone -- the moments of rho and
+ * the Dirichlet ghost shell they give (Sec. 2, Sec. 4), written into the
+ * current state (phi^n and phi^{n-1}), with no substep.  For a residual of a
+ * state set by hgs_set_state against the boundary of a density (the warm
+ * start's check against the zero start).  HGS_ERR_STATE for another bc,
+ * HGS_ERR_ARG for a NULL ctx or rho. */
+hgs_status hgs_multipole_boundary(hgs_ctx* ctx, const void* rho);
+
+/* The zero start as the fallback of a predicted start, decided on the device
+ * in stream order (no synchronisation): after hgs_set_state has set a start,
+ * its residual R_b for rho is computed (bc = MULTIPOLE: with the ghost shell
+ * of rho computed first, as hgs_step does) and, unless the state is finite
+ * and R_b is below the zero start's R_b = 1, the state is reset to
+ * phi^n = phi^{n-1} = 0.  kept (nullable): device int32 set to 1 when the
+ * start was kept, 0 when it was reset.  Errors: HGS_ERR_ARG (NULL ctx or
+ * rho), HGS_ERR_STATE (a local boundary, whose ghosts follow the state). */
+hgs_status hgs_keep_start_if_better(hgs_ctx* ctx, const void* rho, int32_t* kept);
+
+/* The steady state directly: the discrete Dirichlet Poisson problem
+ * L_h phi = 4 pi G rho (Eq. 1, the 7-point Laplacian, the ghosts as boundary
+ * values) -- the fixed point of every damped run, and the Poisson solution the
+ * paper's runs start from (Sec. 2) -- solved by type-I sine transforms along
+ * each axis (the eigenvectors of the 1D second difference with Dirichlet
+ * ends) in FP64; the state becomes phi^n = phi^{n-1} = phi (phidot = 0).
+ * bc = MULTIPOLE: the ghosts are first computed from the moments of rho, as
+ * hgs_step does; bc = USER: the ghosts set by hgs_set_boundary.  rho: device
+ * (nz, ny, nx), storage dtype.  scratch: device memory of at least
+ * 2 nx ny nz doubles, 256-byte aligned, used during the call only.  The cost
+ * is nx ny nz (nx + ny + nz) multiply-adds (dense transforms): meant for
+ * grids up to ~128 per axis.  Errors: HGS_ERR_ARG (NULL ctx or rho, an axis
+ * above 1024 cells), HGS_ERR_STATE (a local boundary), HGS_ERR_WORKSPACE
+ * (scratch missing, too small or misaligned). */
+hgs_status hgs_poisson_direct(hgs_ctx* ctx, const void* rho, void* scratch, size_t bytes);
+
 /* Copy the current potential out; phidot (nullable) receives the backward
  * difference (phi^n - phi^{n-1}) / dt of the last step (zero before any step). */
 hgs_status hgs_potential(hgs_ctx* ctx, void* phi, void* phidot);
@@ -321,9 +355,9 @@ hgs_status hgs_timing_read(hgs_ctx* ctx, int32_t kind, double out[4]);
  * gives grid i's context for every single-grid call (potential, accel,
  * residual, set_state, ...).  hgs_step_batch performs one hydrodynamical step
  * on all grids: per grid the multipole moments and ghosts, then nsub substeps
- * for every grid in launches that each cover all grids (a persistent work list
- * of tiles sorted by cost), replayed from a captured hipGraph of the substep
- * sequence.  Results are bit-identical to stepping each grid alone with the
+ * for every grid in launches that each cover all grids (work items of tiles
+ * and z chunks, see hgs_batch_set_launch), replayed from a captured hipGraph
+ * of the substep sequence.  Results are bit-identical to stepping each grid alone with the
  * same tblock.  Requirements: all grids share storage, stream and tblock (taken
  * from cfgs[0]); every nx is a multiple of the 16-byte vector width (4 for
  * FP32, 2 for FP64). */
@@ -338,6 +372,17 @@ hgs_status hgs_step_batch(hgs_batch* b, const void* const* rho, const double* c_
 /* Whether the last hgs_step_batch replayed a captured graph (1) or fell back
  * to direct launches (0). */
 int32_t hgs_batch_used_graph(const hgs_batch* b);
+/* How the fused substeps of a batch are launched (results are bit-identical):
+ *   HGS_BATCH_PER_ITEM (default): one workgroup per work item, items in grid
+ *     order (z chunks, tile rows, tiles) with a contiguous range per XCD, so
+ *     neighbouring tiles of one grid run together and share halo lines in L2;
+ *     the hardware hands items to CUs as they free up;
+ *   HGS_BATCH_PERSISTENT: one workgroup per CU walking the items in
+ *     decreasing cost, strided (a static longest-first assignment).
+ * HGS_ERR_ARG for another value. */
+typedef enum { HGS_BATCH_PER_ITEM = 0, HGS_BATCH_PERSISTENT = 1 } hgs_batch_launch;
+hgs_status hgs_batch_set_launch(hgs_batch* b, int32_t launch);
+int32_t hgs_batch_get_launch(const hgs_batch* b);
 /* Reason for the batch's last non-OK status ("" if none). */
 const char* hgs_batch_last_error(const hgs_batch* b);
 hgs_status hgs_destroy_batch(hgs_batch* b);

@@ -116,6 +116,33 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
     return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// q = a / d, r = a - q d for a >= 0, d > 0: 32-bit unsigned arithmetic while
+// both fit (every index of the grids and tensors here; a 64-bit division is a
+// long instruction sequence), the 64-bit division otherwise.
+__device__ __forceinline__ int64_t divmod(int64_t a, int64_t d, int64_t& r) {
+    if (a <= 0xffffffffll && d <= 0xffffffffll) {
+        const unsigned q = (unsigned)a / (unsigned)d;
+        r = (int64_t)((unsigned)a - q * (unsigned)d);
+        return q;
+    }
+    const int64_t q = a / d;
+    r = a - q * d;
+    return q;
+}
+
+// (i, j, k) of index c of a compact (nz, ny, nx) array, and the sample b when
+// c runs over several of them
+__device__ __forceinline__ int64_t split3(int64_t c, int nx, int ny, int nz, int& i, int& j, int& k) {
+    int64_t r;
+    int64_t q = divmod(c, nx, r);
+    i = (int)r;
+    q = divmod(q, ny, r);
+    j = (int)r;
+    q = divmod(q, nz, r);
+    k = (int)r;
+    return q;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

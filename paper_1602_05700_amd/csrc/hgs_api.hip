@@ -23,6 +23,7 @@
 #include "k_batch.hpp"
 #include "k_local.hpp"
 #include "k_nest.hpp"
+#include "k_poisson.hpp"
 #include <algorithm>
 #include <cstdlib>
 #include <fstream>
@@ -167,7 +168,11 @@ Plan make_plan(const hgs_config* cfg) {
     p.mom_tx = (cfg->nx + colw - 1) / colw;
     p.mom_ty = (cfg->ny + 3) / 4;
     int cols = p.mom_tx * p.mom_ty;
-    int zsplit = std::max(1, std::min(cfg->nz / kMomMinZ, (2048 + cols - 1) / cols));
+    // small grids would get too few workgroups from kMomMinZ-plane chunks
+    // (32^3: 8 workgroups, 24 us for 128 KB of rho); there chunks go down to 4
+    // planes, since the harmonics per column then cost little in absolute terms
+    const int zmin = (int64_t)cols * (cfg->nz / kMomMinZ) < 512 ? 4 : kMomMinZ;
+    int zsplit = std::max(1, std::min(cfg->nz / zmin, (2048 + cols - 1) / cols));
     p.mom_zc = (cfg->nz + zsplit - 1) / zsplit;
     p.mom_blocks = cols * ((cfg->nz + p.mom_zc - 1) / p.mom_zc);
     size_t off = 4 * p.buf_bytes;
@@ -347,6 +352,32 @@ void run_moments_and_ghosts(hgs_ctx* c, const void* rho, int mask) {
     tm.end((double)sizeof(S) * (double)c->L.nx * c->L.ny * c->L.nz + (double)nb * sizeof(S) * (double)nf, 0.0);
 }
 
+
+// Direct Poisson solve into the state: ghosts of buffer cur (MULTIPOLE: from
+// the moments of rho, written into cur and old; USER: already there), the
+// right-hand side, three sine transforms, the eigenvalue division, three
+// inverse transforms, then phi^n = phi^{n-1} = the solution.
+template <typename S>
+void run_poisson_direct(hgs_ctx* c, const void* rho, double* scratch) {
+    const Layout& L = c->L;
+    if (c->cfg.bc == HGS_BC_MULTIPOLE) run_moments_and_ghosts<S>(c, rho, (1 << c->cur) | (1 << c->old));
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(65536, (n + 255) / 256));
+    double* a = scratch;
+    double* b = scratch + n;
+    const double inv_dx2 = 1.0 / (c->cfg.dx * c->cfg.dx);
+    hipLaunchKernelGGL(k_dst_rhs<S>, dim3(nb), dim3(256), 0, c->stream, static_cast<const S*>(rho), B<S>(c, c->cur),
+                       L, 4.0 * M_PI * c->cfg.G, inv_dx2, a);
+    hipLaunchKernelGGL(k_dst_axis, dim3(nb), dim3(256), 0, c->stream, a, b, L.nx, L.ny, L.nz, 0);
+    hipLaunchKernelGGL(k_dst_axis, dim3(nb), dim3(256), 0, c->stream, b, a, L.nx, L.ny, L.nz, 1);
+    hipLaunchKernelGGL(k_dst_axis, dim3(nb), dim3(256), 0, c->stream, a, b, L.nx, L.ny, L.nz, 2);
+    const double norm = (2.0 / (L.nx + 1)) * (2.0 / (L.ny + 1)) * (2.0 / (L.nz + 1));
+    hipLaunchKernelGGL(k_dst_scale, dim3(nb), dim3(256), 0, c->stream, b, L.nx, L.ny, L.nz, inv_dx2, norm);
+    hipLaunchKernelGGL(k_dst_axis, dim3(nb), dim3(256), 0, c->stream, b, a, L.nx, L.ny, L.nz, 0);
+    hipLaunchKernelGGL(k_dst_axis, dim3(nb), dim3(256), 0, c->stream, a, b, L.nx, L.ny, L.nz, 1);
+    hipLaunchKernelGGL(k_dst_axis, dim3(nb), dim3(256), 0, c->stream, b, a, L.nx, L.ny, L.nz, 2);
+    hipLaunchKernelGGL(k_dst_store<S>, dim3(nb), dim3(256), 0, c->stream, a, L, B<S>(c, c->cur), B<S>(c, c->old));
+}
 
 LocalGeom local_geom(const hgs_ctx* c) {
     return LocalGeom{c->cfg.x0, c->cfg.y0, c->cfg.z0, c->cfg.dx, c->cfg.origin[0], c->cfg.origin[1], c->cfg.origin[2]};
@@ -533,6 +564,12 @@ void run_residual(hgs_ctx* c, const void* rho) {
                        static_cast<const S*>(rho), c->L, idx2, 4.0 * M_PI * c->cfg.G, zc, tx, ty, rbar,
                        local_bc(c->cfg.bc) ? 0 : 1, c->red_partial);
     hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, c->stream, c->red_partial, nb, c->red_out);
+}
+
+template <typename S>
+void run_keep_or_zero(hgs_ctx* c, int32_t* kept) {
+    hipLaunchKernelGGL(k_keep_or_zero<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, c->red_out, c->L,
+                       B<S>(c, c->cur), B<S>(c, c->old), kept);
 }
 
 template <typename S>
@@ -809,6 +846,49 @@ hgs_status hgs_step(hgs_ctx* ctx, const void* rho, double c_g, double dt, int32_
     DISPATCH(ctx, run_substeps, ctx, rho, step_coef(ctx, c_g, dt), nsub, c_g * dt);
     ctx->dt_prev = dt;
     return launch_check(ctx, "hgs_step");
+}
+
+hgs_status hgs_multipole_boundary(hgs_ctx* ctx, const void* rho) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!rho) return fail(ctx, HGS_ERR_ARG, "rho is NULL");
+    if (ctx->cfg.bc != HGS_BC_MULTIPOLE)
+        return fail(ctx, HGS_ERR_STATE, "hgs_multipole_boundary needs bc = HGS_BC_MULTIPOLE");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_moments_and_ghosts, ctx, rho, (1 << ctx->cur) | (1 << ctx->old));
+    ctx->have_moments = true;
+    return launch_check(ctx, "hgs_multipole_boundary");
+}
+
+hgs_status hgs_keep_start_if_better(hgs_ctx* ctx, const void* rho, int32_t* kept) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!rho) return fail(ctx, HGS_ERR_ARG, "rho is NULL");
+    if (local_bc(ctx->cfg.bc))
+        return fail(ctx, HGS_ERR_STATE, "hgs_keep_start_if_better needs a Dirichlet boundary (MULTIPOLE or USER)");
+    (void)hipGetLastError();
+    if (ctx->cfg.bc == HGS_BC_MULTIPOLE) {
+        DISPATCH(ctx, run_moments_and_ghosts, ctx, rho, (1 << ctx->cur) | (1 << ctx->old));
+        ctx->have_moments = true;
+    }
+    DISPATCH(ctx, run_residual, ctx, rho);
+    DISPATCH(ctx, run_keep_or_zero, ctx, kept);
+    return launch_check(ctx, "hgs_keep_start_if_better");
+}
+
+hgs_status hgs_poisson_direct(hgs_ctx* ctx, const void* rho, void* scratch, size_t bytes) {
+    if (!ctx) return fail(nullptr, HGS_ERR_ARG, "ctx is NULL");
+    if (!rho) return fail(ctx, HGS_ERR_ARG, "rho is NULL");
+    if (ctx->cfg.bc != HGS_BC_MULTIPOLE && ctx->cfg.bc != HGS_BC_USER)
+        return fail(ctx, HGS_ERR_STATE, "hgs_poisson_direct needs a Dirichlet boundary (MULTIPOLE or USER)");
+    const Layout& L = ctx->L;
+    if (L.nx > DST_MAXN || L.ny > DST_MAXN || L.nz > DST_MAXN)
+        return fail(ctx, HGS_ERR_ARG, "hgs_poisson_direct: at most 1024 cells per axis");
+    const size_t need = 2 * sizeof(double) * (size_t)L.nx * L.ny * L.nz;
+    if (!scratch || bytes < need || reinterpret_cast<uintptr_t>(scratch) % kAlign)
+        return fail(ctx, HGS_ERR_WORKSPACE, "scratch must hold 2 nx ny nz doubles, 256-byte aligned");
+    (void)hipGetLastError();
+    DISPATCH(ctx, run_poisson_direct, ctx, rho, static_cast<double*>(scratch));
+    if (ctx->cfg.bc == HGS_BC_MULTIPOLE) ctx->have_moments = true;
+    return launch_check(ctx, "hgs_poisson_direct");
 }
 
 hgs_status hgs_potential(hgs_ctx* ctx, void* phi, void* phidot) {
@@ -1120,8 +1200,11 @@ struct hgs_batch {
     hipStream_t stream;
     std::vector<hgs_ctx*> grids;
     void* desc_dev;     // GridDesc<S>[n]
-    WorkItem* tb_items;
+    WorkItem* tb_items;   // fused items in cost order (persistent launch)
     int n_tb_items;
+    WorkItem* tbg_items;  // fused items in grid order (one workgroup per item)
+    int n_tbg_items;
+    int launch;           // hgs_batch_launch
     WorkItem* st_items;
     int n_st_items;
     // host staging of the descriptors, double-buffered: buffer k is refilled
@@ -1131,7 +1214,7 @@ struct hgs_batch {
     bool desc_pending[2];
     int desc_k;
     hipStream_t capture;  // stream used only to record graphs
-    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (nsub, T, cur, old)
+    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (nsub, T, cur, old, launch)
     bool graph_ok;
     bool used_graph;
     std::string err;
@@ -1151,9 +1234,59 @@ hgs_status bfail(hgs_batch* b, hgs_status s, const std::string& m) {
 
 struct BatchPlan {
     std::vector<size_t> grid_off, grid_bytes;
-    size_t desc_off, tb_off, st_off, total;
-    std::vector<WorkItem> tb_items, st_items;
+    size_t desc_off, tb_off, tbg_off, st_off, total;
+    std::vector<WorkItem> tb_items, tbg_items, st_items;
 };
+
+// Fused items of every grid in grid order -- per grid z chunks, then tile
+// rows, then tiles (x fastest), the order of a single-grid launch -- for the
+// launch with one workgroup per item.
+template <typename S>
+void batch_grid_items(const std::vector<Layout>& Ls, int T, int zchunk, std::vector<WorkItem>& tb) {
+    tb.clear();
+    if (T < 2) return;
+    for (int g = 0; g < (int)Ls.size(); ++g) {
+        const Layout& L = Ls[g];
+        int IY = 0;
+        switch (T) {
+            case 2: IY = BatchTile<S, 2>::W * BatchTile<S, 2>::R - 4; break;
+            case 3: IY = BatchTile<S, 3>::W * BatchTile<S, 3>::R - 6; break;
+            default: IY = BatchTile<S, 4>::W * BatchTile<S, 4>::R - 8; break;
+        }
+        const int IX = 64 - 2 * T;
+        const int tx = (L.nx + IX - 1) / IX, ty = (L.ny + IY - 1) / IY;
+        const int zc = std::min(L.nz, zchunk);
+        for (int z = 0; z < L.nz; z += zc)
+            for (int y = 0; y < ty; ++y)
+                for (int x = 0; x < tx; ++x) tb.push_back(WorkItem{g, x, y, z, std::min(L.nz, z + zc)});
+    }
+}
+
+// z-chunk of the grid-ordered items: the hardware hands items to free CUs, so
+// the launch takes about (total pipeline steps) / slots plus the longest item;
+// pick the chunk that minimises that.
+template <typename S>
+int batch_grid_zchunk(const std::vector<Layout>& Ls, int T, int slots) {
+    static const int cand[] = {128, 96, 64, 48, 32, 24, 16, 12, 8};
+    int best = 64;
+    double best_cost = -1.0;
+    std::vector<WorkItem> tb;
+    for (int zc : cand) {
+        if (zc < 2 * T) continue;
+        batch_grid_items<S>(Ls, T, zc, tb);
+        int64_t total = 0, longest = 0;
+        for (const WorkItem& w : tb) {
+            total += w.k1 - w.k0 + 2 * T;
+            longest = std::max<int64_t>(longest, w.k1 - w.k0 + 2 * T);
+        }
+        const double cost = (double)total / slots + (double)longest;
+        if (best_cost < 0.0 || cost < best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+    }
+    return best;
+}
 
 template <typename S>
 void batch_items(const std::vector<Layout>& Ls, int T, int zchunk, std::vector<WorkItem>& tb,
@@ -1265,15 +1398,20 @@ hgs_status batch_plan(const hgs_config* cfgs, int32_t n, BatchPlan& p, std::stri
         off = align_up(off + b, kAlign);
     }
     const int T = default_tblock(&cfgs[0]);
-    if (cfgs[0].storage == HGS_F64)
+    if (cfgs[0].storage == HGS_F64) {
         batch_items<double>(Ls, T, batch_zchunk<double>(Ls, T, kPlanSlots), p.tb_items, p.st_items);
-    else
+        batch_grid_items<double>(Ls, T, batch_grid_zchunk<double>(Ls, T, kPlanSlots), p.tbg_items);
+    } else {
         batch_items<float>(Ls, T, batch_zchunk<float>(Ls, T, kPlanSlots), p.tb_items, p.st_items);
+        batch_grid_items<float>(Ls, T, batch_grid_zchunk<float>(Ls, T, kPlanSlots), p.tbg_items);
+    }
     const size_t dsz = cfgs[0].storage == HGS_F64 ? sizeof(GridDesc<double>) : sizeof(GridDesc<float>);
     p.desc_off = off;
     off = align_up(off + dsz * n, kAlign);
     p.tb_off = off;
     off = align_up(off + sizeof(WorkItem) * std::max<size_t>(1, p.tb_items.size()), kAlign);
+    p.tbg_off = off;
+    off = align_up(off + sizeof(WorkItem) * std::max<size_t>(1, p.tbg_items.size()), kAlign);
     p.st_off = off;
     off = align_up(off + sizeof(WorkItem) * std::max<size_t>(1, p.st_items.size()), kAlign);
     p.total = off;
@@ -1311,6 +1449,33 @@ void batch_launches(hgs_batch* b, int nsub, int cur, int old, hipStream_t st) {
                         o1 = k;
                 }
             const int nb = std::min(b->n_tb_items, ncu);
+            if (b->launch == HGS_BATCH_PER_ITEM) {
+                const dim3 g((unsigned)b->n_tbg_items);
+                switch (T) {
+                    case 2:
+                        hipLaunchKernelGGL((k_tblock_batch_items<S, 2, BatchTile<S, 2>::R, BatchTile<S, 2>::W,
+                                                                 BatchTile<S, 2>::PF, BatchTile<S, 2>::SB,
+                                                                 BatchTile<S, 2>::UPF>),
+                                           g, dim3(64 * BatchTile<S, 2>::W), 0, st, d, b->tbg_items, cur, old, o0, o1);
+                        break;
+                    case 3:
+                        hipLaunchKernelGGL((k_tblock_batch_items<S, 3, BatchTile<S, 3>::R, BatchTile<S, 3>::W,
+                                                                 BatchTile<S, 3>::PF, BatchTile<S, 3>::SB,
+                                                                 BatchTile<S, 3>::UPF>),
+                                           g, dim3(64 * BatchTile<S, 3>::W), 0, st, d, b->tbg_items, cur, old, o0, o1);
+                        break;
+                    default:
+                        hipLaunchKernelGGL((k_tblock_batch_items<S, 4, BatchTile<S, 4>::R, BatchTile<S, 4>::W,
+                                                                 BatchTile<S, 4>::PF, BatchTile<S, 4>::SB,
+                                                                 BatchTile<S, 4>::UPF>),
+                                           g, dim3(64 * BatchTile<S, 4>::W), 0, st, d, b->tbg_items, cur, old, o0, o1);
+                        break;
+                }
+                cur = o0;
+                old = o1;
+                nsub -= T;
+                continue;
+            }
             switch (T) {
                 case 2:
                     hipLaunchKernelGGL((k_tblock_batch<S, 2, BatchTile<S, 2>::R, BatchTile<S, 2>::W, BatchTile<S, 2>::PF,
@@ -1371,7 +1536,7 @@ hgs_status batch_run(hgs_batch* b, int nsub) {
     const int cur = b->grids[0]->cur, old = b->grids[0]->old;
     b->used_graph = false;
     if (b->graph_ok) {
-        auto key = std::make_tuple(nsub, b->tblock, cur, old);
+        auto key = std::make_tuple(nsub, b->tblock, cur, old, b->launch);
         auto it = b->graphs.find(key);
         hipGraphExec_t exec = nullptr;
         if (it != b->graphs.end()) {
@@ -1459,12 +1624,18 @@ hgs_status hgs_init_batch(const hgs_config* cfgs, int32_t n, void* workspace, si
     }
     b->desc_dev = w + p.desc_off;
     b->tb_items = reinterpret_cast<WorkItem*>(w + p.tb_off);
+    b->tbg_items = reinterpret_cast<WorkItem*>(w + p.tbg_off);
     b->st_items = reinterpret_cast<WorkItem*>(w + p.st_off);
     b->n_tb_items = (int)p.tb_items.size();
+    b->n_tbg_items = (int)p.tbg_items.size();
     b->n_st_items = (int)p.st_items.size();
+    b->launch = HGS_BATCH_PER_ITEM;
     hipError_t e = hipSuccess;
     if (!p.tb_items.empty())
         e = hipMemcpyAsync(b->tb_items, p.tb_items.data(), sizeof(WorkItem) * p.tb_items.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !p.tbg_items.empty())
+        e = hipMemcpyAsync(b->tbg_items, p.tbg_items.data(), sizeof(WorkItem) * p.tbg_items.size(),
                            hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->st_items, p.st_items.data(), sizeof(WorkItem) * p.st_items.size(),
@@ -1493,6 +1664,16 @@ hgs_status hgs_batch_grid(hgs_batch* b, int32_t i, hgs_ctx** ctx) {
 }
 
 int32_t hgs_batch_used_graph(const hgs_batch* b) { return b && b->used_graph ? 1 : 0; }
+
+hgs_status hgs_batch_set_launch(hgs_batch* b, int32_t launch) {
+    if (!b) return fail(nullptr, HGS_ERR_ARG, "batch is NULL");
+    if (launch != HGS_BATCH_PER_ITEM && launch != HGS_BATCH_PERSISTENT)
+        return bfail(b, HGS_ERR_ARG, "launch must be HGS_BATCH_PER_ITEM or HGS_BATCH_PERSISTENT");
+    b->launch = launch;
+    return HGS_OK;
+}
+
+int32_t hgs_batch_get_launch(const hgs_batch* b) { return b ? b->launch : -1; }
 
 const char* hgs_batch_last_error(const hgs_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
 

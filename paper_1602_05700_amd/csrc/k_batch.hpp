@@ -66,6 +66,35 @@ __global__ __launch_bounds__(64 * W) void k_tblock_batch(const GridDesc<S>* __re
     }
 }
 
+// The same fused substeps with one workgroup per work item: items are in grid
+// order (z chunks, then tile rows, then tiles, as a single-grid launch walks
+// them) and each XCD takes a contiguous range, so the items resident on an
+// XCD at one time are neighbours of one grid at the same heights and share
+// their halo lines in its L2; the hardware hands items to CUs as they free up.
+template <typename S, int T, int R, int W, int PF, bool SB, bool UPF>
+__global__ __launch_bounds__(64 * W) void k_tblock_batch_items(const GridDesc<S>* __restrict__ grids,
+                                                               const WorkItem* __restrict__ items, int in0,
+                                                               int in1, int out0, int out1) {
+    constexpr int IX = 64 - 2 * T;
+    constexpr int IY = W * R - 2 * T;
+    __shared__ TBShared<S, T, W> sh;
+    const WorkItem wi = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const GridDesc<S>& g = grids[wi.grid];
+    const Layout L = g.L;
+    const StepCoef c = g.c;
+    const int xlo = wi.tx * IX - T, ylo = wi.ty * IY - T;
+    const bool inner = xlo >= 0 && xlo + 64 <= L.nx && ylo >= 0 && ylo + W * R <= L.ny;
+    if (inner) {
+        TBTile<S, T, R, W, PF, SB, UPF, false> t(g.buf[in0], g.buf[in1], g.rho, g.buf[out0], g.buf[out1], L, c, sh,
+                                                 wi.tx, wi.ty, wi.k0, wi.k1);
+        t.run();
+    } else {
+        TBTile<S, T, R, W, PF, SB, UPF, true> t(g.buf[in0], g.buf[in1], g.rho, g.buf[out0], g.buf[out1], L, c, sh,
+                                                wi.tx, wi.ty, wi.k0, wi.k1);
+        t.run();
+    }
+}
+
 // one streaming substep on every grid: buf[cur] is phi^n, buf[old] receives phi^{n+1}
 template <typename S, int BY>
 __global__ __launch_bounds__(64 * BY) void k_stream_batch(const GridDesc<S>* __restrict__ grids,

@@ -396,7 +396,8 @@ __global__ __launch_bounds__(256) void k_wgrad_final(const float* __restrict__ p
 __global__ void k_pack(const float* __restrict__ f, int B, int C, int64_t nvox, uint16_t* __restrict__ out) {
     const int64_t total = (int64_t)B * nvox;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = t / nvox, v = t % nvox;
+        int64_t v;
+        const int64_t b = divmod(t, nvox, v);
         uint16_t h[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) h[c] = c < C ? f2bf(f[(b * C + c) * nvox + v]) : (uint16_t)0;
@@ -530,12 +531,23 @@ __global__ __launch_bounds__(256) void k_maxabs_partial(const float* __restrict_
                                                         float* __restrict__ partial) {
     __shared__ float red[4];
     const int b = blockIdx.y;
-    const int64_t per = (nvox + MAXABS_CHUNKS - 1) / MAXABS_CHUNKS;
+    // chunks of a multiple of 4 values, so that aligned samples are read as
+    // 16-byte vectors with several loads in flight per lane
+    const int64_t per = ((nvox + MAXABS_CHUNKS - 1) / MAXABS_CHUNKS + 3) / 4 * 4;
     const int64_t lo = (int64_t)blockIdx.x * per;
     const int64_t hi = lo + per < nvox ? lo + per : nvox;
     const float* p = x + (int64_t)b * nvox;
     float m = 0.f;
-    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) m = fmaxf(m, fabsf(p[t]));
+    if (lo < hi && nvox % 4 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+        const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll 4
+        for (int64_t t = lo / 4 + threadIdx.x; t < hi / 4; t += blockDim.x) {
+            const float4 v = q[t];
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+    } else {
+        for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) m = fmaxf(m, fabsf(p[t]));
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -567,8 +579,9 @@ __global__ __launch_bounds__(256) void k_features(const float* __restrict__ rho,
                                                   double c, float* __restrict__ out) {
     const int64_t nvox = (int64_t)nz * ny * nx, total = (int64_t)B * nvox;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = t / nvox, v = t % nvox;
-        const int i = (int)(v % nx), j = (int)((v / nx) % ny), k = (int)(v / ((int64_t)nx * ny));
+        int i, j, k;
+        const int64_t b = split3(t, nx, ny, nz, i, j, k);
+        const int64_t v = t - b * nvox;
         const float* pf = phi + t;
         const double lap = (d2_ext(pf, i, nx, 1) + d2_ext(pf, j, ny, nx)) + d2_ext(pf, k, nz, (int64_t)nx * ny);
         const double s = (double)scale[b];
@@ -587,7 +600,8 @@ __global__ __launch_bounds__(256) void k_compose(const float* __restrict__ phi_c
                                                  float* __restrict__ phi, float* __restrict__ phidot) {
     const int64_t total = (int64_t)B * nvox;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const double f = (double)scale[t / nvox] * inv_out;
+        int64_t v;
+        const double f = (double)scale[divmod(t, nvox, v)] * inv_out;
         phi[t] = (float)((double)phi_c[t] + (double)y[t * NC] * f);
         if (phidot) phidot[t] = (float)((double)y[t * NC + 1] * f);
     }
@@ -628,10 +642,8 @@ template <typename T>
 __global__ void k_restrict2(const T* __restrict__ f, int B, int cz, int cy, int cx, T* __restrict__ c) {
     const int64_t total = (int64_t)B * cz * cy * cx;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t % cx);
-        const int j = (int)((t / cx) % cy);
-        const int k = (int)((t / ((int64_t)cx * cy)) % cz);
-        const int64_t b = t / ((int64_t)cx * cy * cz);
+        int i, j, k;
+        const int64_t b = split3(t, cx, cy, cz, i, j, k);
         const int fx = 2 * cx, fy = 2 * cy, fz = 2 * cz;
         double s = 0.0;
         for (int dk = 0; dk < 2; ++dk)
@@ -664,10 +676,8 @@ __global__ void k_prolong2(const T* __restrict__ c, int B, int cz, int cy, int c
     const int fx = 2 * cx, fy = 2 * cy, fz = 2 * cz;
     const int64_t total = (int64_t)B * fz * fy * fx;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(t % fx);
-        const int j = (int)((t / fx) % fy);
-        const int k = (int)((t / ((int64_t)fx * fy)) % fz);
-        const int64_t b = t / ((int64_t)fx * fy * fz);
+        int i, j, k;
+        const int64_t b = split3(t, fx, fy, fz, i, j, k);
         int xi[2], yi[2], zi[2];
         double xw[2], yw[2], zw[2];
         prolong_w(i, cx, xi[0], xw[0], xi[1], xw[1]);

@@ -250,4 +250,26 @@ __global__ __launch_bounds__(256) void k_residual_final(const double* __restrict
     }
 }
 
+// The fallback rule of a predicted start, decided on the device from the
+// residual sums of the state (k_residual_final's out: [sum r^2, sum b^2, ...,
+// non-finite count]): the start is kept when it is finite and its R_b is below
+// the zero start's R_b = 1, i.e. sum r^2 < sum b^2; otherwise the interiors of
+// phi^n and phi^{n-1} are set to zero.  The decision is uniform, so a kept
+// start costs each workgroup one read of two values.
+template <typename S>
+__global__ __launch_bounds__(256) void k_keep_or_zero(const double* __restrict__ red, Layout L, S* __restrict__ p0,
+                                                      S* __restrict__ p1, int32_t* __restrict__ kept) {
+    const bool keep = red[4] == 0.0 && red[0] < red[1];
+    if (kept && blockIdx.x == 0 && threadIdx.x == 0) *kept = keep ? 1 : 0;
+    if (keep) return;
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        split3(c, L.nx, L.ny, L.nz, i, j, k);
+        const int64_t o = L.idx(i, j, k);
+        p0[o] = (S)0;
+        p1[o] = (S)0;
+    }
+}
+
 }  // namespace hgs

@@ -75,6 +75,9 @@ _SIGS = {
     "hgs_nest_ghosts": (_i32, [_vp, _i32, _i32, _i32, _dp, _dbl, _i32, _i32, _i32, _dp, _dbl, _vp, _i32, _vp]),
     "hgs_save_raw": (_i32, [_vp, _vp, _vp, _dp]),
     "hgs_load_raw": (_i32, [_vp, _vp, _vp, _dbl]),
+    "hgs_poisson_direct": (_i32, [_vp, _vp, _vp, _sz]),
+    "hgs_multipole_boundary": (_i32, [_vp, _vp]),
+    "hgs_keep_start_if_better": (_i32, [_vp, _vp, _vp]),
     "hgs_set_tblock": (_i32, [_vp, _i32]),
     "hgs_get_tblock": (_i32, [_vp]),
     "hgs_tile_count": (_i32, [_i32]),
@@ -88,6 +91,8 @@ _SIGS = {
     "hgs_batch_grid": (_i32, [_vp, _i32, ctypes.POINTER(_vp)]),
     "hgs_step_batch": (_i32, [_vp, ctypes.POINTER(_vp), _dp, _dp, _i32]),
     "hgs_batch_used_graph": (_i32, [_vp]),
+    "hgs_batch_set_launch": (_i32, [_vp, _i32]),
+    "hgs_batch_get_launch": (_i32, [_vp]),
     "hgs_batch_last_error": (_cp, [_vp]),
     "hgs_destroy_batch": (_i32, [_vp]),
     "hgs_nn_conv3d": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
@@ -237,11 +242,36 @@ class Solver:
         self._need(rho)
         _check(_lib.hgs_step(self._h, rho.data_ptr(), float(c_g), float(dt), int(nsub)), self._h)
 
-    def potential(self, with_phidot: bool = True):
-        phi = self._new()
+    def potential(self, with_phidot: bool = True, out=None):
+        """(phi, phidot or None); out: an existing tensor for phi."""
+        phi = self._new() if out is None else self._need(out)
         pd = self._new() if with_phidot else None
         _check(_lib.hgs_potential(self._h, phi.data_ptr(), _ptr(pd)), self._h)
         return phi, pd
+
+    def multipole_boundary(self, rho) -> None:
+        """Ghost shell from the moments of rho into the current state (bc = multipole)."""
+        self._need(rho)
+        _check(_lib.hgs_multipole_boundary(self._h, rho.data_ptr()), self._h)
+
+    def keep_start_if_better(self, rho, kept=None):
+        """Reset the state to zero unless its R_b for rho is below the zero
+        start's (decided on the device, no synchronisation); kept: device
+        int32 tensor of one element receiving 1 (kept) or 0 (reset)."""
+        self._need(rho)
+        _check(_lib.hgs_keep_start_if_better(self._h, rho.data_ptr(), _ptr(kept)), self._h)
+        return kept
+
+    def poisson_direct(self, rho, scratch=None):
+        """Set the state to the discrete Dirichlet Poisson solution for rho
+        (phidot = 0); scratch: float64 device tensor of 2 nx ny nz elements
+        (allocated if None)."""
+        self._need(rho)
+        nz, ny, nx = self.shape
+        if scratch is None:
+            scratch = self.torch.empty(2 * nx * ny * nz, dtype=self.torch.float64, device=self.device)
+        _check(_lib.hgs_poisson_direct(self._h, rho.data_ptr(), scratch.data_ptr(),
+                                       scratch.numel() * scratch.element_size()), self._h)
 
     def accel(self, out=None):
         g = [self._new() for _ in range(3)] if out is None else [self._need(t) for t in out]
@@ -616,6 +646,20 @@ class Batch:
     @property
     def used_graph(self) -> bool:
         return bool(_lib.hgs_batch_used_graph(self._h))
+
+    LAUNCHES = {"per_item": 0, "persistent": 1}
+
+    def set_launch(self, launch: str) -> None:
+        """Fused launches with one workgroup per work item ("per_item", the
+        default) or one persistent workgroup per CU ("persistent")."""
+        st = _lib.hgs_batch_set_launch(self._h, self.LAUNCHES[launch])
+        if st != HGS_OK:
+            raise HGSError(st, _lib.hgs_batch_last_error(self._h).decode())
+
+    @property
+    def launch(self) -> str:
+        v = int(_lib.hgs_batch_get_launch(self._h))
+        return {0: "per_item", 1: "persistent"}.get(v, "?")
 
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -5,19 +5,23 @@ The paper starts its runs from a Poisson solution or an interpolated exact one
 (Sec. 2).  Here a start for (phi, dphi/dt) on a fine grid is predicted instead:
 
   1. rho (fine, n^3) is restricted to n/2 and n/4 (2x2x2 means);
-  2. a damped solve of the wave equation on the n/4 grid (multipole boundary,
-     critical damping) gives a coarse potential, prolonged to n/2 -- the global
-     cue a local network cannot build by itself;
+  2. the steady state of the wave equation on the n/4 grid (the discrete
+     Poisson solution with the multipole boundary, by the library's direct
+     sine-transform solve; the network was trained on a 200-substep critically
+     damped solve, which reaches it to ~1e-5) gives a coarse potential,
+     prolonged to n/2 -- the global cue a local network cannot build by itself;
   3. a 4-layer 3x3x3 convolution network (16 channels, tanh, bf16 weights and
      activations, FP32 accumulation) maps (rho, coarse phi, the coarse phi's
      residual of the discrete Eq. 1) at n/2 to a correction of phi and to
      dphi/dt, in units scaled by max(rho) because phi is linear in rho;
   4. the n/2 prediction is prolonged to n and handed to hgs_set_state.
 
-The zero start stays the fallback: if the warm start's residual is not below
-the zero start's, the solver starts from zero.  Steps to a residual tolerance
-count fine substeps; the coarse solve costs (n/4)^3 / n^3 of a fine substep
-per coarse substep and is reported in fine-step equivalents.
+The zero start stays the fallback: start_solver() sets the predicted start
+and keeps it only if its residual R_b is below the zero start's (which is 1),
+else it resets the solver to zero.  Steps to a residual tolerance count fine
+substeps; the coarse cue is reported in fine-step equivalents: a damped solve
+costs (n/4)^3 / n^3 of a fine substep per coarse substep, the direct solve its
+6 (n/4)^4 multiply-adds against ~6 n^3 per fine substep, (n/4)^4 / n^3.
 """
 from __future__ import annotations
 
@@ -157,10 +161,13 @@ class Net:
 class Features:
     """Coarse cue and packed network inputs for a set of fine densities."""
 
-    def __init__(self, n: int, device, coarse_steps: int = 200, lmax: int = 4):
-        self.n, self.device, self.coarse_steps, self.lmax = n, device, coarse_steps, lmax
+    def __init__(self, n: int, device, coarse_steps: int = 200, lmax: int = 4, coarse: str = "direct"):
+        if coarse not in ("direct", "relax"):
+            raise ValueError(f"unknown coarse solve {coarse!r}")
+        self.n, self.device, self.coarse_steps, self.lmax, self.coarse = n, device, coarse_steps, lmax, coarse
         self.nh, self.nq = n // 2, n // 4
         self._batches = {}
+        self._direct = None
 
     def restrict(self, rho):
         """rho: (B, n, n, n) fp32 -> (rho at n/2, rho at n/4)."""
@@ -173,13 +180,34 @@ class Features:
         hgs.nn_restrict2(r2, r4)
         return r2, r4
 
+    def bind_stream(self, stream) -> None:
+        """Issue the coarse solves on `stream` (the library calls go to a
+        solver's own stream; a captured prediction needs the capture stream)."""
+        import torch
+
+        m = self.nq
+        self._direct = (hgs.Solver(m, storage="f32", lmax=self.lmax, device=self.device, stream=stream),
+                        torch.empty(2 * m ** 3, dtype=torch.float64, device=self.device))
+
     def coarse_phi(self, r4):
-        """Damped solves on the n/4 grids (one batch), prolonged to n/2.  The
-        batch of grids is kept per batch size and restarted from zero on every
-        call (its ghosts are rebuilt by the first substep group)."""
+        """Coarse potentials on the n/4 grids, prolonged to n/2: the direct
+        Poisson solve of each coarse density (coarse = "direct"), or the damped
+        solve the network was trained on (coarse = "relax")."""
         import torch
 
         B, m = r4.shape[0], self.nq
+        if self.coarse == "direct":
+            if self._direct is None:
+                self._direct = (hgs.Solver(m, storage="f32", lmax=self.lmax, device=self.device),
+                                torch.empty(2 * m ** 3, dtype=torch.float64, device=r4.device))
+            sv, scratch = self._direct
+            phi4 = torch.empty((B, m, m, m), dtype=torch.float32, device=r4.device)
+            for i in range(B):
+                sv.poisson_direct(r4[i], scratch)
+                sv.potential(with_phidot=False, out=phi4[i])
+            phi2 = torch.empty((B, self.nh, self.nh, self.nh), dtype=torch.float32, device=r4.device)
+            hgs.nn_prolong2(phi4, phi2)
+            return phi2
         dx = 2.0 / m
         if B not in self._batches:
             # two substeps per fused launch: on 32^3 grids a launch is bound by
@@ -201,6 +229,8 @@ class Features:
 
     @property
     def coarse_cost_fine_steps(self) -> float:
+        if self.coarse == "direct":
+            return self.nq ** 4 / self.n ** 3
         return self.coarse_steps * (self.nq / self.n) ** 3
 
     def inputs(self, rho):
@@ -213,7 +243,10 @@ class Features:
         r2, r4 = self.restrict(rho)
         phi2 = self.coarse_phi(r4)
         scale = torch.empty(B, dtype=torch.float32, device=rho.device)
-        hgs.nn_maxabs(rho, scale)
+        if B <= hgs.NN_MAXABS_NOALLOC_MAX_B:
+            hgs.nn_maxabs_noalloc(rho, scale)  # no scratch buffer: capturable as it is
+        else:
+            hgs.nn_maxabs(rho, scale)
         h = 2.0 * (2.0 / self.n)
         planar = torch.empty((B, IN_CH) + tuple(r2.shape[1:]), dtype=torch.float32, device=rho.device)
         hgs.nn_features(r2, phi2, scale, 4.0 * math.pi * h * h, planar)
@@ -247,6 +280,64 @@ def predict_fine(net: Net, planar, phi2, scale, n: int):
     return phi, pd
 
 
+class Predictor:
+    """The whole prediction for B densities of n^3 cells -- restriction, the
+    coarse direct solve, features, the network, composition and prolongation
+    (about two dozen library launches) -- captured once into a HIP graph and
+    replayed, so its cost is the kernels' and not their launches'.  The input
+    is copied into a buffer the graph reads; the outputs are buffers the graph
+    writes (overwritten by the next call)."""
+
+    def __init__(self, net: Net, n: int, B: int = 1, device="cuda"):
+        import torch
+
+        self.net, self.n, self.B = net, n, B
+        self.stream = torch.cuda.Stream(device=device)
+        self.feats = Features(n, device, coarse_steps=net.coarse_steps)
+        self.feats.bind_stream(self.stream)
+        self.rho = torch.zeros((B, n, n, n), dtype=torch.float32, device=device)
+        self.rho.fill_(1.0)
+        with torch.cuda.stream(self.stream):
+            # eager pass first: the library and torch allocate what they need
+            # outside the capture
+            planar, phi2, scale = self.feats.inputs(self.rho)
+            predict_fine(net, planar, phi2, scale, n)
+        self.stream.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            planar, phi2, scale = self.feats.inputs(self.rho)
+            self.phi, self.pd = predict_fine(net, planar, phi2, scale, n)
+
+    def __call__(self, rho):
+        """rho: (B, n, n, n) fp32 -> (phi, phidot), (B, n, n, n) fp32 each,
+        ordered on the current stream."""
+        import torch
+
+        cur = torch.cuda.current_stream(self.rho.device)
+        self.rho.copy_(rho)
+        self.stream.wait_stream(cur)
+        self.graph.replay()
+        cur.wait_stream(self.stream)
+        return self.phi, self.pd
+
+
+def start_solver(solver, rho, phi, phidot, dt: float):
+    """Hand a predicted start (phi, phidot) to the solver, with the zero start
+    as the fallback: the start is kept if its residual R_b (the residual of
+    the discrete Eq. 1 relative to the linear system's right-hand side, with
+    the multipole boundary of rho) is below the zero start's, which is 1 by
+    construction; otherwise the solver is reset to the zero start.  Decided on
+    the device in stream order (hgs_keep_start_if_better): returns a device
+    int32 tensor holding 1 (kept) or 0 (reset), read without blocking the
+    stream's work."""
+    import torch
+
+    solver.set_state(phi, phidot, dt)
+    kept = torch.empty(1, dtype=torch.int32, device=phi.device)
+    solver.keep_start_if_better(rho, kept)
+    return kept
+
+
 def converged_phi(rhos, n: int, device, steps: int = 1500, storage: str = "f64", lmax: int = 4):
     """Potentials of the damped solver run to convergence (the training targets),
     for a list of (n, n, n) densities; one batch of grids."""
@@ -268,8 +359,10 @@ def steps_to_tolerance(rho, n: int, tol: float, start=None, max_steps: int = 400
     from zero or from start = (phi, phidot).  metric: "R_b" (the residual
     relative to the linear system's right-hand side, boundary terms
     included), "R_f" (relative to the source alone) or "E" (relative
-    distance to the converged potential ref).  Returns (steps, criterion
-    after the first check, criterion at the end)."""
+    distance to the converged potential ref).  A start goes through
+    start_solver (the zero start is the fallback).  Returns (steps, criterion
+    after the first check, criterion at the end, whether the start was
+    kept)."""
     import torch
 
     if metric not in ("R_b", "R_f", "E"):
@@ -284,8 +377,9 @@ def steps_to_tolerance(rho, n: int, tol: float, start=None, max_steps: int = 400
     r = rho.to(dtype).contiguous()
     # one step of zero length is not allowed; set the ghosts with a first step of
     # `check` substeps from the chosen start and count those substeps
+    kept = None
     if start is not None:
-        s.set_state(start[0].to(dtype).contiguous(), start[1].to(dtype).contiguous(), dt)
+        kept = start_solver(s, r, start[0].to(dtype).contiguous(), start[1].to(dtype).contiguous(), dt)
     if metric == "E":
         ref64 = ref.to(torch.float64)
         ref_norm = float(ref64.norm())
@@ -302,5 +396,6 @@ def steps_to_tolerance(rho, n: int, tol: float, start=None, max_steps: int = 400
             r0 = rb
         if rb < tol:
             break
+    used = bool(kept.item()) if kept is not None else False
     s.close()
-    return steps, r0, rb
+    return steps, r0, rb, used

@@ -175,6 +175,29 @@ def test_lapmse_matches_oracle(gpu_lib, shape):
     assert np.all(_h(grad)[..., C:] == 0)
 
 
+@pytest.mark.parametrize("shape", [(3, 64, 64, 64), (2, 33, 40, 48), (1, 1, 1, 4), (2, 16, 3, 20), (4, 1, 1, 260)])
+def test_maxabs_vector_path(gpu_lib, shape):
+    """Per-sample max |x| over samples whose voxel count is a multiple of 4
+    (16-byte loads, chunks that may be empty) and a peak in a chunk's last
+    vector; the scratch-free call gives the same values."""
+    import torch
+
+    rng = np.random.default_rng(17)
+    a = rng.normal(0.0, 1.0, shape).astype(np.float32)
+    B = shape[0]
+    flat = a.reshape(B, -1)
+    flat[0, -1] = 50.0
+    flat[B - 1, flat.shape[1] // 2] = -70.0
+    want = np.abs(flat).max(axis=1)
+    x = _t(a, torch.float32)
+    s = torch.empty(B, dtype=torch.float32, device="cuda")
+    gpu_lib.nn_maxabs(x, s)
+    assert np.array_equal(_h(s), want.astype(np.float64))
+    s2 = torch.empty(B, dtype=torch.float32, device="cuda")
+    gpu_lib.nn_maxabs_noalloc(x, s2)
+    assert torch.equal(s, s2)
+
+
 def test_features_maxabs_compose_match_oracle(gpu_lib):
     import torch
 

@@ -111,6 +111,28 @@ def test_moments_and_ghosts(gpu_lib, shape, storage, origin):
         assert rel(got, want) < tol, lmax
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_multipole_boundary_alone(gpu_lib, storage):
+    """hgs_multipole_boundary gives the ghost shell hgs_step computes (the
+    oracle's), with the state left as it was set."""
+    import torch
+
+    shape = (23, 29, 37)
+    g = grid_of(shape)
+    rho = dens(shape, 11, storage)
+    s = solver(gpu_lib, shape, storage=storage, lmax=4)
+    phi0 = torch.full(shape, -0.5, dtype=s.dtype, device="cuda")
+    s.set_state(phi0, None, 0.1)
+    s.multipole_boundary(to_dev(rho))
+    P = core.padded(g)
+    core.boundary(g, core.moments(g, rho.astype(np.float64), 4), 4, 1.0, P)
+    tol = 1e-12 if storage == "f64" else 1e-7
+    assert rel(host(s.get_boundary()), gpu_lib.faces_to_flat(core.faces(P))) < tol
+    assert torch.equal(s.potential(with_phidot=False)[0], phi0)
+    with pytest.raises(gpu_lib.HGSError):
+        solver(gpu_lib, shape, storage=storage, bc="user").multipole_boundary(to_dev(rho))
+
+
 def test_moments_match_legendre_brute_force(gpu_lib):
     """The GPU ghost shell against the addition theorem summed over cells."""
     shape = (9, 11, 10)
@@ -586,6 +608,66 @@ def test_config_256_rotating_blobs(gpu_lib, storage):
     assert rel_vec([host(a) for a in s.accel()], o.accel()) < tol
 
 
+# ------------------------------------------------------------------ direct Poisson solve
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 7, 9), (23, 29, 37), (32, 32, 32), (40, 33, 64)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_poisson_direct_matches_dst_oracle(gpu_lib, shape, storage):
+    """hgs_poisson_direct (sine transforms on the GPU) against the oracle's
+    DST-I solve of the same discrete Dirichlet problem with the multipole
+    ghosts of the same density (l <= 4, an off-centre origin): 1e-10 in FP64
+    storage, the stored FP32 rounding in FP32; the state is a fixed point of
+    the damped substeps (R_b at rounding level) and phidot is zero."""
+    g = grid_of(shape)
+    origin = (0.03, -0.02, 0.01)
+    rho = dens(shape, 21, storage)
+    s = solver(gpu_lib, shape, storage=storage, lmax=4, eta=2.0, origin=origin)
+    s.poisson_direct(to_dev(rho))
+    phi, pd = s.potential()
+    q = core.moments(g, rho.astype(np.float64), 4, origin)
+    P = core.padded(g)
+    core.boundary(g, q, 4, 1.0, P, origin)
+    want = poisson.solve_dst(g, rho.astype(np.float64), 1.0, P)
+    tol = 1e-10 if storage == "f64" else 2e-7
+    assert rel(host(phi), want) < tol
+    assert np.all(host(pd) == 0.0)
+    rb = s.residual(to_dev(rho))[0]
+    assert rb < (1e-12 if storage == "f64" else 1e-5), rb
+    if min(shape) > 1:
+        before = host(s.potential()[0])
+        s.step(to_dev(rho), 1.0, 0.4 * g.dx, 8)
+        assert rel(host(s.potential()[0]), before) < (1e-12 if storage == "f64" else 2e-6)
+
+
+def test_poisson_direct_user_boundary_and_errors(gpu_lib):
+    """With caller ghosts (bc = USER) the solve uses them as they are: a
+    quadratic potential with rho uniform is reproduced to rounding (the
+    7-point Laplacian is exact on quadratics).  Local boundaries, a missing or
+    short scratch are refused."""
+    import torch
+
+    shape = (12, 10, 14)
+    g = grid_of(shape)
+    rho0 = 0.7
+    x, y, z = workloads.centred_axes(shape, g.dx)
+    quad = lambda X, Y, Z: (2 * math.pi / 3) * rho0 * (X ** 2 + Y ** 2 + Z ** 2)
+    P = core.padded(g)
+    xs, ys, zs = (np.concatenate(([a[0] - g.dx], a, [a[-1] + g.dx])) for a in (x, y, z))
+    Zp, Yp, Xp = np.meshgrid(zs, ys, xs, indexing="ij")
+    P[...] = quad(Xp, Yp, Zp)
+    s = solver(gpu_lib, shape, storage="f64", bc="user")
+    s.set_boundary(to_dev(gpu_lib.faces_to_flat(core.faces(P))))
+    s.poisson_direct(torch.full(shape, rho0, dtype=torch.float64, device="cuda"))
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    assert rel(host(s.potential()[0]), quad(X, Y, Z)) < 1e-12
+    short = torch.empty(10, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu_lib.HGSError):
+        s.poisson_direct(torch.zeros(shape, dtype=torch.float64, device="cuda"), short)
+    r = solver(gpu_lib, shape, storage="f64", bc="robin")
+    with pytest.raises(gpu_lib.HGSError):
+        r.poisson_direct(torch.zeros(shape, dtype=torch.float64, device="cuda"))
+
+
 # ------------------------------------------------------------------ temporal blocking
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -668,15 +750,20 @@ def test_tblock_against_oracle(gpu_lib, storage, tile):
 # ------------------------------------------------------------------ batched grids
 
 @pytest.mark.parametrize("storage", ["f32", "f64"])
-@pytest.mark.parametrize("tblock", [4, 1])
-def test_batch_bitwise_equals_single_grids(gpu_lib, storage, tblock):
+@pytest.mark.parametrize("tblock", [4, 3, 1])
+@pytest.mark.parametrize("launch", ["per_item", "persistent"])
+def test_batch_bitwise_equals_single_grids(gpu_lib, storage, tblock, launch):
     """A batch of uneven grids stepped together (graph replay, fused launches
-    covering all grids) equals each grid stepped alone, bit for bit."""
+    covering all grids, either launch form) equals each grid stepped alone,
+    bit for bit."""
     import torch
 
-    shapes = [(32, 32, 32), (20, 24, 16), (48, 40, 64), (9, 11, 8), (64, 64, 64)]
+    shapes = [(32, 32, 32), (20, 24, 16), (48, 40, 64), (9, 11, 8), (64, 64, 64), (150, 36, 24)]
     b = gpu_lib.Batch(shapes, dxs=[grid_of(sh).dx for sh in shapes], x0s=[corner(sh) for sh in shapes],
                       storage=storage, tblock=tblock, eta=0.3, lmax=4)
+    assert b.launch == "per_item"
+    b.set_launch(launch)
+    assert b.launch == launch
     singles = [solver(gpu_lib, sh, storage=storage, tblock=tblock, eta=0.3, lmax=4) for sh in shapes]
     rhos = [to_dev(dens(sh, 30 + i, storage)) for i, sh in enumerate(shapes)]
     for dtf, nsub in [(0.4, 9), (0.4, 9), (0.3, 6)]:

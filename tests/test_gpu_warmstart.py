@@ -87,15 +87,16 @@ def test_small_end_to_end(gpu_lib):
     assert losses[-1] < 0.5 * losses[0]
     phi, pd = ws.predict_fine(net, planar[:1].contiguous(), phi2[:1].contiguous(), scale[:1], n)
     assert phi.shape == (1, n, n, n) and torch.isfinite(phi).all() and torch.isfinite(pd).all()
-    steps, r0, rb = ws.steps_to_tolerance(rho[0], n, 1e-4, start=(phi[0], pd[0]))
+    steps, r0, rb, _ = ws.steps_to_tolerance(rho[0], n, 1e-4, start=(phi[0], pd[0]))
     assert rb < 1e-4 and steps < 4000
 
 
 def test_committed_weights_cut_steps_threefold(gpu_lib):
     """The trained network shipped with the package, on held-out 128^3
     densities: substeps of the damped FP32 solver to R_b < 1e-4 from its warm
-    start (coarse solve counted in fine-substep equivalents) against the zero
-    start.  The median gain must reach 3x with no fallback to the zero start."""
+    start (through start_solver, the coarse cue counted in fine-substep
+    equivalents) against the zero start.  The median gain must reach 3x with
+    no fallback to the zero start."""
     import os
 
     import torch
@@ -116,6 +117,65 @@ def test_committed_weights_cut_steps_threefold(gpu_lib):
     for i in range(len(seeds)):
         zero = ws.steps_to_tolerance(rho[i], n, 1e-4)
         warm = ws.steps_to_tolerance(rho[i], n, 1e-4, start=(phi[i], pd[i]))
-        assert warm[1] < zero[1] and warm[2] < 1e-4
+        assert warm[3] and warm[1] < zero[1] and warm[2] < 1e-4
         ratios.append(zero[0] / (warm[0] + feats.coarse_cost_fine_steps))
     assert np.median(ratios) >= 3.0, ratios
+
+
+def test_start_solver_falls_back_to_zero(gpu_lib):
+    """start_solver keeps a start whose residual R_b is below the zero start's
+    (1) and otherwise resets the solver to zero: a start far off the solution
+    (R_b > 1) is refused, the state is then zero, and the direct Poisson
+    solution of the same density (R_b ~ 0) is kept."""
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import hgs, warmstart as ws
+
+    n = 32
+    dx = 2.0 / n
+    rho = workloads.blob_density_torch(n, workloads.warmstart_blobs(3), "cuda", torch.float32)
+    s = hgs.Solver(n, storage="f32", lmax=4, eta=ws.eta_critical(n, dx))
+    bad = torch.full((n, n, n), 50.0, dtype=torch.float32, device="cuda")
+    assert ws.start_solver(s, rho, bad, None, 0.4 * dx).item() == 0
+    phi, pd = s.potential()
+    assert torch.count_nonzero(phi) == 0 and torch.count_nonzero(pd) == 0
+    assert s.residual(rho)[0] == pytest.approx(1.0, abs=1e-12)  # the zero start, with rho's ghosts
+    nan = bad.clone()
+    nan[3, 4, 5] = float("nan")
+    assert ws.start_solver(s, rho, nan, None, 0.4 * dx).item() == 0
+    assert torch.count_nonzero(s.potential(with_phidot=False)[0]) == 0
+    ref = hgs.Solver(n, storage="f32", lmax=4)
+    ref.poisson_direct(rho)
+    good = ref.potential(with_phidot=False)[0]
+    assert ws.start_solver(s, rho, good, torch.zeros_like(good), 0.4 * dx).item() == 1
+    assert torch.equal(s.potential(with_phidot=False)[0], good)
+    assert s.residual(rho)[0] < 1e-5
+    r = hgs.Solver(n, storage="f32", bc="robin")
+    with pytest.raises(hgs.HGSError):
+        r.keep_start_if_better(rho)
+
+
+def test_captured_predictor_matches_eager_prediction(gpu_lib):
+    """The graph-captured prediction equals the eager one bit for bit, replay
+    after replay, with other densities and eager library work in between."""
+    import torch
+
+    import workloads
+    from paper_1602_05700_amd import hgs, warmstart as ws
+
+    n = 64
+    net = ws.Net.load(ws.WEIGHTS, "cuda")
+    pred = ws.Predictor(net, n, B=1, device="cuda")
+    feats = ws.Features(n, "cuda", coarse_steps=net.coarse_steps)
+    other = hgs.Solver(32, storage="f32", lmax=4, eta=1.0)
+    r_other = workloads.blob_density_torch(32, workloads.warmstart_blobs(99), "cuda", torch.float32)
+    for seed in (20000, 20001, 20000, 20002):
+        rho = workloads.blob_density_torch(n, workloads.warmstart_blobs(seed), "cuda", torch.float32)[None]
+        planar, phi2, scale = feats.inputs(rho)
+        want = ws.predict_fine(net, planar, phi2, scale, n)
+        got = pred(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], want[0]) and torch.equal(got[1], want[1]), seed
+        other.step(r_other, 1.0, 0.4 * 2 / 32, 8)  # eager work between replays
+        torch.cuda.synchronize()
