@@ -169,11 +169,13 @@ def run_batched(dev, nsub=500, seed=2, count=64):
         b.set_launch(launch)
         b.step(rhos, 1.0, dts, nsub)  # warm-up: captures the graph of this launch form
         torch.cuda.synchronize()
+        log(f"[bench]   batched {launch}: warmed up")
         e0.record(b.stream)
         for _ in range(reps):
             b.step(rhos, 1.0, dts, nsub)
         e1.record(b.stream)
         torch.cuda.synchronize()
+        log(f"[bench]   batched {launch}: timed")
         return e0.elapsed_time(e1) / reps
 
     ms_persistent = timed("persistent")
@@ -595,6 +597,8 @@ def main():
                     help="storage of the headline run (f32: the headline configuration; f64 for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-grid batched measurement")
+    ap.add_argument("--batch-substeps", type=int, default=500,
+                    help="substeps per hydro step of the batched measurement (fewer for profiler runs)")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the steps-to-1e-4 warm-start measurement")
     ap.add_argument("--no-configs", action="store_true", help="skip the 64^3 sphere and 256^3 rotating-blob runs")
     ap.add_argument("--no-study", action="store_true", help="skip the boundary-placement error study")
@@ -760,8 +764,8 @@ def main():
     log(f"[bench] five more blocks of {K} hydro steps: {reps} Gcell-updates/s")
     del rhos
     if not args.no_batched:
-        log("[bench] batched: 64 uneven grids, 500 substeps")
-        line["batched"] = run_batched(dev)
+        log(f"[bench] batched: 64 uneven grids, {args.batch_substeps} substeps")
+        line["batched"] = run_batched(dev, nsub=args.batch_substeps)
         log(f"[bench]   {line['batched']}")
     if not args.no_configs:
         log("[bench] smaller configurations: 64^3 sphere (FP64), 256^3 rotating blobs (FP64, FP32)")
