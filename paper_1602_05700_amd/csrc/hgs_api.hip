@@ -273,11 +273,13 @@ struct Timed {
 // ---- launches, templated on the storage type ---------------------------------
 
 constexpr int SBX = 64, SBY = 4;  // streaming tile (scalar kernels)
-// Rows per workgroup of the 16-byte gradient, measured at 512^3 FP32: 472 us
-// at 8 rows (z chunks of 16 planes), 476 at 4, 481 at 16.  The kernel is
-// bound by its three output streams; the extra z-halo reads of the shorter
-// chunks do not show.
-constexpr int GBY = 8;
+// Gradient tile: GR rows per thread, GBY waves.  Measured at 512^3 FP32 (us
+// per launch, z chunks of 16 planes unless noted): 4 x 2 428, 8 x 1 429,
+// 4 x 4 430, 4 x 8 430, 2 x 4 446; 4 x 2 with 32 and 64 planes 462 and 450;
+// one row per thread in 8 waves (each row loaded again by the threads above
+// and below it) 475.  Bound by its three output streams (12 of its ~16.5
+// bytes per cell in FP32).
+constexpr int GR = 4, GBY = 2;
 
 // Tiles of bx x by columns marching up z chunks of >= 16 planes, with enough
 // workgroups to fill every CU several times over.
@@ -457,8 +459,8 @@ void launch_gradient(hgs_ctx* c, const S* phi, const Layout& W, void* gx, void* 
     int zc, tx, ty, nb;
     Timed tm(c, HGS_KERNEL_GRADIENT);
     if (vec) {
-        stream_dims(W, 64 * Vec16<S>::N, zc, tx, ty, nb, GBY);
-        hipLaunchKernelGGL((k_gradient_v<S, GBY>), dim3(nb), dim3(64, GBY), 0, c->stream, phi, W, 0.5 / c->cfg.dx, zc,
+        stream_dims(W, 64 * Vec16<S>::N, zc, tx, ty, nb, GR * GBY);
+        hipLaunchKernelGGL((k_gradient_v<S, GR, GBY>), dim3(nb), dim3(64, GBY), 0, c->stream, phi, W, 0.5 / c->cfg.dx, zc,
                            tx, ty, static_cast<S*>(gx), static_cast<S*>(gy), static_cast<S*>(gz));
     } else {
         stream_dims(W, SBX, zc, tx, ty, nb);

@@ -229,7 +229,14 @@ __global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restri
     stream_v_tile<S, BY>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz), rbar ? *rbar : 0.0);
 }
 
-template <typename S, int BY>
+// Central-difference gradient, 16 bytes per lane along x, R rows per thread:
+// each thread marches up its z chunk with a three-plane window of its R rows
+// in registers, so a row is loaded once per plane (plus the two rows that
+// border the thread's rows in y) instead of once for itself and once for
+// each y neighbour.  g = -(phi(+1) - phi(-1)) / (2 dx) per axis in FP64,
+// rounded to the storage type; outputs are compact, written with streaming
+// stores.
+template <typename S, int R, int BY>
 __global__ __launch_bounds__(64 * BY) void k_gradient_v(const S* __restrict__ phi, Layout L, double half_inv_dx,
                                                         int zc, int tiles_x, int tiles_y, S* __restrict__ gx,
                                                         S* __restrict__ gy, S* __restrict__ gz) {
@@ -240,49 +247,76 @@ __global__ __launch_bounds__(64 * BY) void k_gradient_v(const S* __restrict__ ph
     const int tx = bid % tiles_x;
     const int ty = (bid / tiles_x) % tiles_y;
     const int tz = bid / (tiles_x * tiles_y);
-    const VLane g = vlane<N>(L, tx, ty, BY);
     const int lane = threadIdx.x;
+    const int i0 = (tx * 64 + lane) * N;
+    const bool x_act = i0 < L.nx;
+    const int xl = min(i0, L.nx);      // [nx, nx+N) lies inside the row padding
+    const int xr = min(i0, L.nx - N);  // an in-bounds output column for idle lanes
+    const int jb = ty * (BY * R) + (int)threadIdx.y * R;
     const int k0 = tz * zc;
     const int k1 = min(k0 + zc, L.nz);
     const int64_t plane = L.plane;
-    const int pitch = L.pitch;
-    const S* pc = phi + L.idx(g.xl, g.jl, k0);
     const int64_t sxy = (int64_t)L.nx * L.ny;
-    const int64_t c0 = (int64_t)k0 * sxy + (int64_t)g.jr * L.nx + g.xr;
-    VT* ox = reinterpret_cast<VT*>(gx + c0);
-    VT* oy = reinterpret_cast<VT*>(gy + c0);
-    VT* oz = reinterpret_cast<VT*>(gz + c0);
-    const int64_t vsxy = sxy / N;
-    VT zm = *reinterpret_cast<const VT*>(pc - plane);
-    VT z0 = *reinterpret_cast<const VT*>(pc);
-    for (int k = k0; k < k1; ++k) {
-        const VT zp = *reinterpret_cast<const VT*>(pc + plane);
-        const VT ym = *reinterpret_cast<const VT*>(pc - pitch);
-        const VT yp = *reinterpret_cast<const VT*>(pc + pitch);
-        S left = from_prev(V::get(z0, N - 1));
-        S right = from_next(V::get(z0, 0));
-        if (lane == 0) left = pc[-1];
-        if (lane == 63) right = pc[N];
-        VT ax, ay, az;
+    // padded offsets of the thread's rows (clamped into the ghost box) and of
+    // the rows below and above them; compact output offsets
+    int64_t ro[R], co[R];
+    bool act[R];
 #pragma unroll
-        for (int n = 0; n < N; ++n) {
-            const double xm = n > 0 ? (double)V::get(z0, n - 1) : (double)left;
-            const double xp = n < N - 1 ? (double)V::get(z0, n + 1) : (double)right;
-            V::set(ax, n, (S)(-(xp - xm) * half_inv_dx));
-            V::set(ay, n, (S)(-((double)V::get(yp, n) - (double)V::get(ym, n)) * half_inv_dx));
-            V::set(az, n, (S)(-((double)V::get(zp, n) - (double)V::get(zm, n)) * half_inv_dx));
+    for (int r = 0; r < R; ++r) {
+        const int j = jb + r;
+        act[r] = x_act && j < L.ny;
+        ro[r] = L.idx(xl, min(j, L.ny), k0);
+        co[r] = (int64_t)k0 * sxy + (int64_t)min(j, L.ny - 1) * L.nx + xr;
+    }
+    const int64_t rm = L.idx(xl, min(jb - 1, L.ny), k0);
+    const int64_t rp = L.idx(xl, min(jb + R, L.ny), k0);
+    VT zm[R], z0[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        zm[r] = *reinterpret_cast<const VT*>(phi + ro[r] - plane);
+        z0[r] = *reinterpret_cast<const VT*>(phi + ro[r]);
+    }
+    int64_t pin = 0, pout = 0;
+    for (int k = k0; k < k1; ++k) {
+        VT zp[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) zp[r] = *reinterpret_cast<const VT*>(phi + ro[r] + pin + plane);
+        const VT below = *reinterpret_cast<const VT*>(phi + rm + pin);
+        const VT above = *reinterpret_cast<const VT*>(phi + rp + pin);
+        S left[R], right[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            left[r] = from_prev(V::get(z0[r], N - 1));
+            right[r] = from_next(V::get(z0[r], 0));
+            if (lane == 0) left[r] = phi[ro[r] + pin - 1];
+            if (lane == 63) right[r] = phi[ro[r] + pin + N];
         }
-        if (g.active) {
-            __builtin_nontemporal_store(ax, ox);
-            __builtin_nontemporal_store(ay, oy);
-            __builtin_nontemporal_store(az, oz);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const VT& ym = r > 0 ? z0[r - 1] : below;
+            const VT& yp = r < R - 1 ? z0[r + 1] : above;
+            VT ax, ay, az;
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                const double xm = n > 0 ? (double)V::get(z0[r], n - 1) : (double)left[r];
+                const double xp = n < N - 1 ? (double)V::get(z0[r], n + 1) : (double)right[r];
+                V::set(ax, n, (S)(-(xp - xm) * half_inv_dx));
+                V::set(ay, n, (S)(-((double)V::get(yp, n) - (double)V::get(ym, n)) * half_inv_dx));
+                V::set(az, n, (S)(-((double)V::get(zp[r], n) - (double)V::get(zm[r], n)) * half_inv_dx));
+            }
+            if (act[r]) {
+                __builtin_nontemporal_store(ax, reinterpret_cast<VT*>(gx + co[r] + pout));
+                __builtin_nontemporal_store(ay, reinterpret_cast<VT*>(gy + co[r] + pout));
+                __builtin_nontemporal_store(az, reinterpret_cast<VT*>(gz + co[r] + pout));
+            }
         }
-        zm = z0;
-        z0 = zp;
-        pc += plane;
-        ox += vsxy;
-        oy += vsxy;
-        oz += vsxy;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            zm[r] = z0[r];
+            z0[r] = zp[r];
+        }
+        pin += plane;
+        pout += sxy;
     }
 }
 
