@@ -350,7 +350,11 @@ def run_tracking(dev, n=256, nsub=4, steps=250, every=5, omega=0.1):
 def run_next_rows(dev, n=256, nsub=4, steps=20):
     """Throughput of the parts built beyond the multipole path, at 256^3 FP32
     on the same 8-blob density (eta = 0, dt = 0.4 dx): the local boundaries
-    (one substep per launch plus a ghost launch), the extended grid (32 vacuum
+    (at the depth and tile the autotuner picks: Robin and periodic can fuse
+    substeps, the ghosts of both new levels set after each fused launch;
+    outgoing runs one substep per launch plus a ghost launch), Robin and
+    periodic again at 512^3 with one and with four substeps per launch, the
+    extended grid (32 vacuum
     cells on every side, outgoing boundary, rho embedded every hydro step, g on
     the hydrodynamics region; updates counted over the whole wider grid), the
     nested coarse outer levels (Robin at the outermost faces; one level 16 or
@@ -385,9 +389,28 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
 
     g = [torch.empty((n, n, n), dtype=torch.float32, device=dev) for _ in range(3)]
     for bc in ("robin", "outgoing", "periodic"):
-        sv = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, bc=bc, device=dev)
+        # the depth and tile the autotuner picks for this boundary and size
+        best, tile, _ = hgs.autotune((n, n, n), rho, 1.0, dt, nsub, storage="f32", bc=bc, device=dev)
+        sv = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, bc=bc, device=dev, tblock=best, tile=tile)
         timed(bc, lambda: (sv.step(rho, 1.0, dt, nsub), sv.accel(g)), n ** 3 * nsub)
+        res[bc]["substeps_per_launch"] = 1 if bc == "outgoing" else sv.tblock
+        res[bc]["tile"] = tile
         sv.close()
+    # Robin and periodic at 512^3, where a streamed substep is bound by HBM
+    # (at 256^3 a field fits the last-level cache and streaming gains from
+    # it): one substep per launch against four fused
+    n5 = 512
+    rho5 = workloads.blob_density_torch(n5, workloads.blob_params(0, 8), dev, torch.float32)
+    g5 = [torch.empty((n5, n5, n5), dtype=torch.float32, device=dev) for _ in range(3)]
+    dt5 = 0.4 * 2.0 / n5
+    for bc in ("robin", "periodic"):
+        for T, tile in ((1, 0), (4, 1)):
+            sv = hgs.Solver(n5, storage="f32", lmax=4, eta=0.0, bc=bc, device=dev, tblock=T, tile=tile)
+            label = f"{bc}_512_t{T}"
+            timed(label, lambda: (sv.step(rho5, 1.0, dt5, nsub), sv.accel(g5)), n5 ** 3 * nsub)
+            res[label]["substeps_per_launch"] = T
+            sv.close()
+    del rho5, g5
     e = 32
     ex = hgs.ExtendedSolver(n, e, bc="outgoing", storage="f32", lmax=4, eta=0.0, device=dev)
     timed("extended_outgoing_ext32", lambda: (ex.step(rho, 1.0, dt, nsub), ex.accel()), (n + 2 * e) ** 3 * nsub)

@@ -106,6 +106,41 @@ __device__ __forceinline__ double ld(const S* p) {
     return (double)(*p);
 }
 
+// Cell-centre positions relative to the expansion centre, for the outer
+// boundaries whose ghosts follow the interior (Robin, outgoing).
+struct LocalGeom {
+    double x0, y0, z0, dx, ox, oy, oz;
+};
+
+// Coordinate of cell index i along one axis (lo = that axis's grid corner,
+// o = the centre's coordinate), rounded to the storage type.
+template <typename S>
+__device__ __forceinline__ S local_coord(double lo, double o, double dx, int i) {
+    return (S)(lo + ((double)i + 0.5) * dx - o);
+}
+
+// |x|^2 in the storage type, in one fixed order of operations.
+template <typename S>
+__device__ __forceinline__ S local_r2(S x, S y, S z) {
+    return fma(x, x, fma(y, y, z * z));
+}
+
+// Robin ghost (Sec. 2, Sec. 4: a monopole far field, r phi equal at the ghost
+// and its interior neighbour) from the neighbour's value v:
+// v |x_i| / |x_g| = v sqrt(|x_i|^2 / |x_g|^2) in the storage type: FP64 with
+// the correctly rounded divide and square root; FP32 with the hardware
+// reciprocal and square root (a few ulp, far below the FP32 storage
+// rounding of the state, and a handful of instructions where the fused
+// launch evaluates it once per face cell and level).  Every kernel that sets
+// or reads a Robin ghost calls this with the same operands, so streamed and
+// fused substeps agree bit for bit.
+__device__ __forceinline__ double robin_ghost(double ri2, double rg2, double v) {
+    return v * sqrt(ri2 / rg2);
+}
+__device__ __forceinline__ float robin_ghost(float ri2, float rg2, float v) {
+    return v * __builtin_amdgcn_sqrtf(ri2 * __builtin_amdgcn_rcpf(rg2));
+}
+
 // Workgroups of one launch are handed to the 8 XCDs round-robin.  Renumber
 // them so that XCD x runs a contiguous range of tiles: neighbouring tiles then
 // share that XCD's L2 for their halos.

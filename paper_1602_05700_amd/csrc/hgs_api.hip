@@ -303,6 +303,16 @@ bool use_vec(const Layout& L) {
 // hydrodynamical step (multipole, user).
 bool local_bc(int bc) { return bc == HGS_BC_ROBIN || bc == HGS_BC_OUTGOING || bc == HGS_BC_PERIODIC; }
 
+// Substeps per launch: the fused depth, except for the outgoing rule (its
+// ghost depends on its own previous level, so every substep is a launch of
+// its own) and for Robin or periodic grids thinner than two cells (a cell
+// there borders both faces of an axis).
+int fused_depth(const hgs_ctx* c) {
+    if (c->cfg.bc == HGS_BC_OUTGOING) return 1;
+    if (local_bc(c->cfg.bc) && std::min(c->cfg.nx, std::min(c->cfg.ny, c->cfg.nz)) < 2) return 1;
+    return c->tblock;
+}
+
 // Buffers that hold phi^n at some point of the coming nsub substeps, the
 // last state included: a fused launch reads (cur, old) and makes the other
 // two buffers (phi^{n+T}, phi^{n+T-1}); a streaming substep writes the new
@@ -310,7 +320,7 @@ bool local_bc(int bc) { return bc == HGS_BC_ROBIN || bc == HGS_BC_OUTGOING || bc
 // update reads phi^{n-1} at the cell alone), so only they need this
 // hydrodynamical step's ghosts.  Bit k of the result = buffer k.
 int ghost_buffers(const hgs_ctx* c, int nsub) {
-    const int T = local_bc(c->cfg.bc) ? 1 : c->tblock;
+    const int T = fused_depth(c);
     int cur = c->cur, old = c->old;
     int mask = 1 << cur;
     while (nsub > 0) {
@@ -409,7 +419,9 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
     const S* r = static_cast<const S*>(rho);
     const bool local = local_bc(c->cfg.bc);
     const double* rbar = c->cfg.bc == HGS_BC_PERIODIC ? c->mean : nullptr;
-    int T = local ? 1 : c->tblock;
+    const int T = fused_depth(c);
+    const TBBound bnd{c->cfg.bc == HGS_BC_ROBIN ? TB_ROBIN : (c->cfg.bc == HGS_BC_PERIODIC ? TB_PERIODIC : TB_FROZEN),
+                      local_geom(c), c->mean};
     while (nsub > 0) {
         if (T > 1 && nsub >= T) {
             // out of place: (cur, old) -> (the other two buffers)
@@ -423,9 +435,15 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
                 }
             Timed tm(c, HGS_KERNEL_STENCIL);
             launch_tblock<S>(B<S>(c, c->cur), B<S>(c, c->old), r, B<S>(c, o0), B<S>(c, o1), c->L, sc, T, c->tile, c->ncu,
-                             c->stream);
+                             c->stream, bnd);
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(5.0 * sizeof(S) * cells, cells * T);
+            if (local) {
+                // Robin and periodic ghosts of both new levels: the rule's
+                // value from each level's own interior
+                run_local_ghosts<S>(c, o0, -1, c_dt);
+                run_local_ghosts<S>(c, o1, -1, c_dt);
+            }
             c->cur = o0;
             c->old = o1;
             nsub -= T;
@@ -1789,7 +1807,7 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
     s = validate_step(nullptr, cfg, rho, c_g, dt, nsub);
     if (s != HGS_OK) return s;
     if (best_tile) *best_tile = 0;
-    if (local_bc(cfg->bc)) {  // one substep per launch: nothing to choose
+    if (cfg->bc == HGS_BC_OUTGOING) {  // one substep per launch: nothing to choose
         *best_tblock = 1;
         if (ms_per_substep)
             for (int i = 0; i < HGS_TMAX; ++i) ms_per_substep[i] = -1.0;

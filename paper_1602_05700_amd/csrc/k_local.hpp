@@ -21,10 +21,6 @@
 
 namespace hgs {
 
-struct LocalGeom {
-    double x0, y0, z0, dx, ox, oy, oz;
-};
-
 // One thread per face ghost; grid (ceil(max(nx, ny) / 256), max(ny, nz), 6),
 // face f = blockIdx.z in the order x-, x+, y-, y+, z-, z+.  In-face index
 // (a, b): x faces (j, k), y faces (i, k), z faces (i, j).  nxt holds the new
@@ -52,6 +48,18 @@ __global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int
         nxt[pg] = nxt[L.idx(op[0], op[1], op[2])];
         return;
     }
+    if (bc == HGS_BC_ROBIN || cur == nullptr) {
+        // Robin (and the steady form of the outgoing rule)
+        const S ci[3] = {local_coord<S>(g.x0, g.ox, g.dx, in[0]), local_coord<S>(g.y0, g.oy, g.dx, in[1]),
+                         local_coord<S>(g.z0, g.oz, g.dx, in[2])};
+        S cg[3] = {ci[0], ci[1], ci[2]};
+        cg[axis] = axis == 0   ? local_coord<S>(g.x0, g.ox, g.dx, gh[0])
+                   : axis == 1 ? local_coord<S>(g.y0, g.oy, g.dx, gh[1])
+                               : local_coord<S>(g.z0, g.oz, g.dx, gh[2]);
+        nxt[pg] = robin_ghost(local_r2(ci[0], ci[1], ci[2]), local_r2(cg[0], cg[1], cg[2]), nxt[pi]);
+        return;
+    }
+    // outgoing: the box scheme above, in FP64
     const double lo[3] = {g.x0 - g.ox, g.y0 - g.oy, g.z0 - g.oz};
     double xg[3], xi[3];
     for (int d = 0; d < 3; ++d) {
@@ -60,18 +68,13 @@ __global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int
     }
     const double rg = sqrt(xg[0] * xg[0] + xg[1] * xg[1] + xg[2] * xg[2]);
     const double ri = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
-    double v;
-    if (bc == HGS_BC_ROBIN || cur == nullptr) {
-        v = ri * (double)nxt[pi] / rg;
-    } else {
-        const double xf[3] = {0.5 * (xg[0] + xi[0]), 0.5 * (xg[1] + xi[1]), 0.5 * (xg[2] + xi[2])};
-        const double rf = sqrt(xf[0] * xf[0] + xf[1] * xf[1] + xf[2] * xf[2]);
-        const double cth = (hi ? xf[axis] : -xf[axis]) / rf;
-        const double al = c_dt / (g.dx * cth);
-        const double ug0 = rg * (double)cur[pg], ui0 = ri * (double)cur[pi], ui1 = ri * (double)nxt[pi];
-        const double ug1 = ((1.0 - al) * ug0 + (1.0 + al) * ui0 - (1.0 - al) * ui1) / (1.0 + al);
-        v = ug1 / rg;
-    }
+    const double xf[3] = {0.5 * (xg[0] + xi[0]), 0.5 * (xg[1] + xi[1]), 0.5 * (xg[2] + xi[2])};
+    const double rf = sqrt(xf[0] * xf[0] + xf[1] * xf[1] + xf[2] * xf[2]);
+    const double cth = (hi ? xf[axis] : -xf[axis]) / rf;
+    const double al = c_dt / (g.dx * cth);
+    const double ug0 = rg * (double)cur[pg], ui0 = ri * (double)cur[pi], ui1 = ri * (double)nxt[pi];
+    const double ug1 = ((1.0 - al) * ug0 + (1.0 + al) * ui0 - (1.0 - al) * ui1) / (1.0 + al);
+    const double v = ug1 / rg;
     nxt[pg] = (S)v;
 }
 

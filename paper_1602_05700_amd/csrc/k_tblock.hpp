@@ -24,6 +24,17 @@
 // value at every level.  Every level is rounded to the storage type exactly as
 // a streaming launch stores it, so any T gives bit-identical results.
 //
+// Outer boundaries.  Frozen ghosts (multipole, user) keep their input value
+// at every level.  Robin ghosts follow the interior at every level: an
+// interior cell beside a face reads its ghost neighbour as the Robin value of
+// its own level (the ghost is a multiple of that cell alone), so no ghost
+// needs a value of its own inside the launch; the launch's host then sets the
+// ghosts of both output levels by the same rule.  Periodic: there are no
+// ghosts, the tile's cells wrap around the grid (every cell is an interior
+// one), and the source is rho minus the domain mean.  Each gives the
+// streaming substeps' results bit for bit.  The outgoing rule, whose ghost
+// depends on its own previous level, stays with streaming substeps.
+//
 // The plane loop is unrolled by U = lcm(3, 2, T, PF) so that the three-plane
 // windows, the LDS slot parity, the ring of rho planes and the prefetch ring
 // rotate by compile-time index instead of register moves.  Tiles whose
@@ -59,6 +70,15 @@ struct Unroll {
     static constexpr int U = tb_lcm(tb_lcm(6, T), PF);
 };
 
+constexpr int TB_FROZEN = 0, TB_ROBIN = 1, TB_PERIODIC = 2;
+
+__device__ __forceinline__ int wrap(int i, int n) {
+    const int m = i % n;
+    return m < 0 ? m + n : m;
+}
+// the same for -n <= i < 2n, without a division
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
 template <typename S, int T, int W>
 struct TBShared {
     S edge[T][2][W][2][64];  // [level][slot][wave][0 first row, 1 last row][lane]
@@ -72,7 +92,8 @@ struct TBShared {
 //     clamped loads read planes that are never used: no branch and no ring
 //     copies), else only while planes remain.
 // Which is faster depends on the shape and depth (measured; see TileSet).
-template <typename S, int T, int R, int W, int PF, bool SB, bool UPF, bool EDGE>
+// BND: TB_FROZEN, TB_ROBIN or TB_PERIODIC (above)
+template <typename S, int T, int R, int W, int PF, bool SB, bool UPF, bool EDGE, int BND = TB_FROZEN>
 struct TBTile {
     static constexpr int IX = 64 - 2 * T;
     static constexpr int IY = W * R - 2 * T;
@@ -88,6 +109,14 @@ struct TBTile {
     TBShared<S, T, W>& sh;
     int64_t plane, cplane;  // elements per padded / compact plane
     int nz, k0, k1;
+    double rb;  // TB_PERIODIC: domain-mean density subtracted from rho
+    // TB_ROBIN: which faces this thread's cells touch, the coordinates
+    // (storage type) of its cells, and the ghost layers' coordinates
+    // (x = -1 and nx, and so on; the same for every thread)
+    LocalGeom lg;
+    bool fxl, fxh, fyl[R], fyh[R];
+    S cxi, cyi[R];
+    S gx0, gx1, gy0, gy1, gz0, gz1;
     // per-thread constants.  Addresses are a uniform plane base plus a 32-bit
     // byte offset, so loads and stores take the scalar-base form and need no
     // per-access 64-bit address arithmetic.
@@ -102,8 +131,9 @@ struct TBTile {
     S pn[PF][R], po[PF][R], pr[PF][R];  // prefetch ring
 
     __device__ TBTile(const S* a, const S* b, const S* rh, S* o0, S* o1, const Layout& L, const StepCoef& cc,
-                      TBShared<S, T, W>& s, int tx, int ty, int kk0, int kk1)
-        : in_n(a), in_nm1(b), rho(rh), out_n(o0), out_nm1(o1), c(cc), sh(s) {
+                      TBShared<S, T, W>& s, int tx, int ty, int kk0, int kk1, const LocalGeom& geo = LocalGeom{},
+                      double rbar = 0.0)
+        : in_n(a), in_nm1(b), rho(rh), out_n(o0), out_nm1(o1), c(cc), sh(s), rb(rbar), lg(geo) {
         plane = L.plane;
         cplane = (int64_t)L.nx * L.ny;
         nz = L.nz;
@@ -117,19 +147,36 @@ struct TBTile {
         wp = w < W - 1 ? w + 1 : W - 1;
         const bool x_in = x >= 0 && x < L.nx;
         const bool x_out = x_in && lane >= T && lane < T + IX;
-        const int xc = min(max(x, -1), L.nx);
-        const int xr = min(max(x, 0), L.nx - 1);
+        // periodic: every cell of the tile is the interior cell it wraps onto
+        const int xc = BND == TB_PERIODIC ? wrap(x, L.nx) : min(max(x, -1), L.nx);
+        const int xr = BND == TB_PERIODIC ? xc : min(max(x, 0), L.nx - 1);
+        if (BND == TB_ROBIN) {
+            fxl = x == 0;
+            fxh = x == L.nx - 1;
+            cxi = local_coord<S>(lg.x0, lg.ox, lg.dx, x);
+            gx0 = local_coord<S>(lg.x0, lg.ox, lg.dx, -1);
+            gx1 = local_coord<S>(lg.x0, lg.ox, lg.dx, L.nx);
+            gy0 = local_coord<S>(lg.y0, lg.oy, lg.dx, -1);
+            gy1 = local_coord<S>(lg.y0, lg.oy, lg.dx, L.ny);
+            gz0 = local_coord<S>(lg.z0, lg.oz, lg.dx, -1);
+            gz1 = local_coord<S>(lg.z0, lg.oz, lg.dx, L.nz);
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = y0 + r;
             const int er = w * R + r;
             const bool y_in = y >= 0 && y < L.ny;
-            in_ok[r] = x_in && y_in;
+            in_ok[r] = BND == TB_PERIODIC || (x_in && y_in);
             out_ok[r] = x_out && y_in && er >= T && er < T + IY;
-            const int yc = min(max(y, -1), L.ny);
-            const int yr = min(max(y, 0), L.ny - 1);
+            const int yc = BND == TB_PERIODIC ? wrap(y, L.ny) : min(max(y, -1), L.ny);
+            const int yr = BND == TB_PERIODIC ? yc : min(max(y, 0), L.ny - 1);
             bp[r] = (uint32_t)(((yc + HALO) * L.pitch + (xc + L.xoff)) * (int)sizeof(S));
             bc[r] = (uint32_t)((yr * L.nx + xr) * (int)sizeof(S));
+            if (BND == TB_ROBIN) {
+                fyl[r] = y == 0;
+                fyh[r] = y == L.ny - 1;
+                cyi[r] = local_coord<S>(lg.y0, lg.oy, lg.dx, y);
+            }
         }
 #pragma unroll
         for (int t = 0; t < T; ++t)
@@ -154,8 +201,9 @@ struct TBTile {
     // valid cell.
     template <int B>
     __device__ __forceinline__ void load(int p) {
-        const int pc = min(max(p, -1), nz);
-        const int qc = min(max(p - 1, 0), nz - 1);
+        // periodic: planes p in [k0 - T, k1 + T) wrap once when nz > T
+        const int pc = BND == TB_PERIODIC ? (nz > T ? wrap1(p, nz) : wrap(p, nz)) : min(max(p, -1), nz);
+        const int qc = BND == TB_PERIODIC ? (nz > T ? wrap1(p - 1, nz) : wrap(p - 1, nz)) : min(max(p - 1, 0), nz - 1);
         const S* bn = in_n + (int64_t)(pc + HALO) * plane;
         const S* bo = in_nm1 + (int64_t)(qc + HALO) * plane;
         const S* br = rho + (int64_t)qc * cplane;
@@ -167,7 +215,7 @@ struct TBTile {
             if (SB) asm("" : "+v"(op), "+v"(oc));
             pn[B][r] = at(bn, op);
             po[B][r] = at(bo, op);
-            pr[B][r] = at(br, oc);
+            pr[B][r] = BND == TB_PERIODIC ? source(at(br, oc), rb) : at(br, oc);
         }
     }
 
@@ -195,17 +243,57 @@ struct TBTile {
             // holds plane q in OLD (its NEW is q+2).  Planes outside the grid
             // (the ghost plane and the clamped ring below and above it) keep
             // their input value (a select on a uniform condition).
-            const bool z_in = q >= 0 && q < nz;
+            const bool z_in = BND == TB_PERIODIC || (q >= 0 && q < nz);
+            S zz = (S)0;
+            if (BND == TB_ROBIN) {
+                const S cz = local_coord<S>(lg.z0, lg.oz, lg.dx, q);
+                zz = cz * cz;
+            }
             S nv[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const S ce = win[t - 1][MID][r];
-                    const S zm = win[t - 1][OLD][r];
-                    const S zp = win[t - 1][NEW][r];
-                    const S ym = (r > 0) ? win[t - 1][MID][r - 1] : sh.edge[t - 1][PREV][wm][1][lane];
-                    const S yp = (r < R - 1) ? win[t - 1][MID][r + 1] : sh.edge[t - 1][PREV][wp][0][lane];
-                    const S xm = (S)lane_prev(ce);
-                    const S xp = (S)lane_next(ce);
+                    S zm = win[t - 1][OLD][r];
+                    S zp = win[t - 1][NEW][r];
+                    S ym = (r > 0) ? win[t - 1][MID][r - 1] : sh.edge[t - 1][PREV][wm][1][lane];
+                    S yp = (r < R - 1) ? win[t - 1][MID][r + 1] : sh.edge[t - 1][PREV][wp][0][lane];
+                    S xm = (S)lane_prev(ce);
+                    S xp = (S)lane_next(ce);
+                    // Robin: a ghost neighbour is the Robin value of this cell's
+                    // own level (robin_ghost on the operands the ghost launch
+                    // uses); x and y faces only in tiles that reach them, z faces
+                    // in any tile at the first and last plane
+                    if (BND == TB_ROBIN && EDGE) {
+                        if (fxl || fxh) {
+                            const S yz = fma(cyi[r], cyi[r], zz);
+                            const S cg = fxl ? gx0 : gx1;
+                            const S g = robin_ghost(fma(cxi, cxi, yz), fma(cg, cg, yz), ce);
+                            if (fxl)
+                                xm = g;
+                            else
+                                xp = g;
+                        }
+                        if (fyl[r] || fyh[r]) {
+                            const S cg = fyl[r] ? gy0 : gy1;
+                            const S g = robin_ghost(fma(cxi, cxi, fma(cyi[r], cyi[r], zz)),
+                                                    fma(cxi, cxi, fma(cg, cg, zz)), ce);
+                            if (fyl[r])
+                                ym = g;
+                            else
+                                yp = g;
+                        }
+                    }
+                    if (BND == TB_ROBIN) {
+                        if (q == 0 || q == nz - 1) {
+                            const S cg = q == 0 ? gz0 : gz1;
+                            const S g = robin_ghost(fma(cxi, cxi, fma(cyi[r], cyi[r], zz)),
+                                                    fma(cxi, cxi, fma(cyi[r], cyi[r], cg * cg)), ce);
+                            if (q == 0)
+                                zm = g;
+                            else
+                                zp = g;
+                        }
+                    }
                     const S ol = (t == 1) ? old1[r] : win[t >= 2 ? t - 2 : 0][OLD][r];
                     const int RS = ((PH - t + 1) % T + T) % T;  // ring slot of rho(p - t)
                     const S v = (S)update(c, ce, xm, xp, ym, yp, zm, zp, ol, rq[RS][r]);
@@ -261,11 +349,14 @@ struct TBTile {
     }
 };
 
-template <typename S, int T, int R, int W, int PF, bool SB, bool UPF>
+// BND: TB_FROZEN, TB_ROBIN (lg: cell positions) or TB_PERIODIC (rbar: device
+// pointer to the domain-mean density)
+template <typename S, int T, int R, int W, int PF, bool SB, bool UPF, int BND>
 __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict__ in_n, const S* __restrict__ in_nm1,
                                                             const S* __restrict__ rho, S* __restrict__ out_n,
                                                             S* __restrict__ out_nm1, Layout L, StepCoef c, int zc,
-                                                            int tiles_x, int tiles_y) {
+                                                            int tiles_x, int tiles_y, LocalGeom lg,
+                                                            const double* __restrict__ rbar) {
     constexpr int IX = 64 - 2 * T;
     constexpr int IY = W * R - 2 * T;
     static_assert(IX > 0 && IY > 0, "tile too small for the temporal depth");
@@ -278,14 +369,18 @@ __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict_
     const int tz = bid / (tiles_x * tiles_y);
     const int k0 = tz * zc;
     const int k1 = min(k0 + zc, L.nz);
-    // the extended tile lies strictly inside the grid: no per-cell boundary work
+    // the extended tile lies strictly inside the grid: no per-cell boundary
+    // work across x and y
     const int xlo = tx * IX - T, ylo = ty * IY - T;
     const bool inner = xlo >= 0 && xlo + 64 <= L.nx && ylo >= 0 && ylo + W * R <= L.ny;
+    const double rb = BND == TB_PERIODIC ? *rbar : 0.0;
     if (inner) {
-        TBTile<S, T, R, W, PF, SB, UPF, false> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1);
+        TBTile<S, T, R, W, PF, SB, UPF, false, BND> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1, lg,
+                                                      rb);
         t.run();
     } else {
-        TBTile<S, T, R, W, PF, SB, UPF, true> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1);
+        TBTile<S, T, R, W, PF, SB, UPF, true, BND> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1, lg,
+                                                     rb);
         t.run();
     }
 }
@@ -370,36 +465,66 @@ struct TileSet<S, 4> {
 
 inline int tile_count(int T) { return T == 4 ? 3 : (T >= 2 ? 2 : 1); }
 
-template <typename S, int T, int I>
+// Outer boundary of a fused launch: mode (TB_*), cell positions (Robin) and
+// the device mean density (periodic)
+struct TBBound {
+    int mode;
+    LocalGeom lg;
+    const double* rbar;
+};
+
+template <typename S, int T, int I, int BND>
 void launch_tblock_shape(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
-                         const StepCoef& c, int ncu, hipStream_t st) {
+                         const StepCoef& c, int ncu, hipStream_t st, const TBBound& b) {
     constexpr TileShape sh = TileSet<S, T>::at(I);
     const TBlockDims d = tblock_dims<T, sh.R, sh.W>(L, ncu);
-    hipLaunchKernelGGL((k_leapfrog_tblock<S, T, sh.R, sh.W, sh.PF, sh.SB, sh.UPF>), dim3(d.nblocks), dim3(64 * sh.W),
-                       0, st, in_n, in_nm1, rho, out_n, out_nm1, L, c, d.zc, d.tiles_x, d.tiles_y);
+    hipLaunchKernelGGL((k_leapfrog_tblock<S, T, sh.R, sh.W, sh.PF, sh.SB, sh.UPF, BND>), dim3(d.nblocks),
+                       dim3(64 * sh.W), 0, st, in_n, in_nm1, rho, out_n, out_nm1, L, c, d.zc, d.tiles_x, d.tiles_y,
+                       b.lg, b.rbar);
+}
+
+template <typename S, int T, int I>
+void launch_tblock_bnd(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
+                       const StepCoef& c, int ncu, hipStream_t st, const TBBound& b) {
+    switch (b.mode) {
+        case TB_ROBIN: {
+            // FP32 depth 4: shape 0 with the Robin terms exceeds the 128
+            // registers a 16-wave workgroup allows and spills; shape 1 (one
+            // plane fewer in flight) fits.  Shapes give identical results.
+            constexpr int IR = (sizeof(S) == 4 && T == 4 && I == 0) ? 1 : I;
+            launch_tblock_shape<S, T, IR, TB_ROBIN>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
+            break;
+        }
+        case TB_PERIODIC:
+            launch_tblock_shape<S, T, I, TB_PERIODIC>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
+            break;
+        default: launch_tblock_shape<S, T, I, TB_FROZEN>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
+    }
 }
 
 template <typename S, int T>
 void launch_tblock_t(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
-                     const StepCoef& c, int tile, int ncu, hipStream_t st) {
+                     const StepCoef& c, int tile, int ncu, hipStream_t st, const TBBound& b) {
     if constexpr (TileSet<S, T>::N > 2) {
-        if (tile == 2) return launch_tblock_shape<S, T, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st);
+        if (tile == 2) return launch_tblock_bnd<S, T, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
     }
     if constexpr (TileSet<S, T>::N > 1) {
-        if (tile == 1) return launch_tblock_shape<S, T, 1>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st);
+        if (tile == 1) return launch_tblock_bnd<S, T, 1>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
     }
-    launch_tblock_shape<S, T, 0>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st);
+    launch_tblock_bnd<S, T, 0>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
 }
 
 // ncu: compute units of the device (one resident workgroup of this kernel
-// each); tile: index into TileSet<S, T> (a depth with fewer shapes takes 0)
+// each); tile: index into TileSet<S, T> (a depth with fewer shapes takes 0);
+// b: the outer boundary (frozen ghosts by default)
 template <typename S>
 void launch_tblock(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
-                   const StepCoef& c, int T, int tile, int ncu, hipStream_t st) {
+                   const StepCoef& c, int T, int tile, int ncu, hipStream_t st,
+                   const TBBound& b = TBBound{TB_FROZEN, LocalGeom{}, nullptr}) {
     switch (T) {
-        case 2: launch_tblock_t<S, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st); break;
-        case 3: launch_tblock_t<S, 3>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st); break;
-        case 4: launch_tblock_t<S, 4>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st); break;
+        case 2: launch_tblock_t<S, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st, b); break;
+        case 3: launch_tblock_t<S, 3>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st, b); break;
+        case 4: launch_tblock_t<S, 4>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st, b); break;
         default: break;
     }
 }

@@ -140,14 +140,71 @@ def test_outgoing_checkpoint_bitwise(gpu_lib, storage):
     assert np.array_equal(host(a.get_boundary()), host(b.get_boundary()))
 
 
-def test_local_bc_rejected_in_batch_and_tuned_to_one(gpu_lib):
+def test_local_bc_rejected_in_batch_and_tuned(gpu_lib):
+    """Local boundaries are refused in batches; the autotuner returns depth 1
+    for the outgoing rule without timing and times every depth for Robin and
+    periodic, which fuse substeps."""
     hgs = gpu_lib
     with pytest.raises(hgs.HGSError):
         hgs.Batch([16, 32], bc="robin", storage="f32", device="cuda")
     rho = to_dev(dens((16, 16, 16), 27, "f32"))
-    best, tile, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc="periodic",
+    best, tile, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc="outgoing",
                                      device="cuda")
-    assert best == 1 and tile == 0
+    assert best == 1 and tile == 0 and times is None
+    for bc in ("robin", "periodic"):
+        best, tile, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc=bc,
+                                         device="cuda")
+        assert 1 <= best <= 4 and 0 <= tile < max(1, hgs.tile_count(best)) and all(t > 0 for t in times)
+
+
+@pytest.mark.parametrize("bc", ["robin", "periodic"])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(2, 2, 2), (7, 9, 5), (23, 29, 37), (40, 33, 130), (70, 61, 66), (9, 150, 67)])
+@pytest.mark.parametrize("T,tile", [(4, 0), (4, 1), (4, 2), (3, 0), (3, 1), (2, 0), (2, 1)])
+def test_fused_local_bc_bitwise_equals_streaming(gpu_lib, bc, storage, shape, T, tile):
+    """Robin and periodic substeps fused T per launch give the streaming
+    results bit for bit: the potential, phi^{n-1}, the ghost faces and g,
+    over hydro steps whose substep counts are and are not multiples of T,
+    with a dt change (phi^{n-1} rescaled), on grids smaller than one tile,
+    with ragged tiles in every direction, and more tiles in y than in x."""
+    import torch
+
+    g = grid_of(shape)
+    rho = to_dev(dens(shape, 28, storage))
+    origin = (0.03, -0.02, 0.01)
+    a = solver(gpu_lib, shape, storage=storage, eta=0.7, origin=origin, bc=bc, tblock=1)
+    b = solver(gpu_lib, shape, storage=storage, eta=0.7, origin=origin, bc=bc, tblock=T, tile=tile)
+    assert a.tblock == 1 and b.tblock == T
+    for dt, nsub in [(0.4, T), (0.4, 2 * T + 1), (0.3, 5), (0.45, 3 * T)]:
+        a.step(rho, 1.0, dt * g.dx, nsub)
+        b.step(rho, 1.0, dt * g.dx, nsub)
+    ra, rb = a.save_raw(), b.save_raw()
+    torch.cuda.synchronize()
+    assert torch.equal(ra[0], rb[0]) and torch.equal(ra[1], rb[1])
+    assert torch.equal(a.get_boundary(), b.get_boundary())
+    assert all(torch.equal(u, v) for u, v in zip(a.accel(), b.accel()))
+
+
+@pytest.mark.parametrize("bc", ["robin", "periodic"])
+def test_fused_local_bc_against_oracle_256(gpu_lib, bc):
+    """At 256^3 FP32 (fused depth 4, the launch the bench times for these
+    boundaries) two hydro steps against the FP64 oracle at the FP32 bar."""
+    import torch
+
+    import workloads
+    from oracle.core import Grid
+
+    n = 256
+    g = Grid.cube(n)
+    rho = workloads.blob_density_torch(n, workloads.blob_params(0, 8), "cuda", torch.float32)
+    r64 = rho.double().cpu().numpy()
+    origin = (0.03, -0.02, 0.01)
+    s = gpu_lib.Solver(n, storage="f32", eta=0.5, bc=bc, origin=origin, tblock=4)
+    o = Oracle(g, eta=0.5, bc=bc, origin=origin)
+    for _ in range(2):
+        s.step(rho, 1.0, 0.4 * g.dx, 4)
+        o.step(r64, 1.0, 0.4 * g.dx, 4)
+    compare_state(s, o, "f32", F32_TOL)
 
 
 def test_periodic_and_energy_256_against_oracle(gpu_lib):
