@@ -109,6 +109,7 @@ struct TBTile {
     TBShared<S, T, W>& sh;
     int64_t plane, cplane;  // elements per padded / compact plane
     int nz, k0, k1;
+    bool down;  // march the chunk from its top plane downwards
     double rb;  // TB_PERIODIC: domain-mean density subtracted from rho
     // TB_ROBIN: which faces this thread's cells touch, the coordinates
     // (storage type) of its cells, and the ghost layers' coordinates
@@ -132,8 +133,8 @@ struct TBTile {
 
     __device__ TBTile(const S* a, const S* b, const S* rh, S* o0, S* o1, const Layout& L, const StepCoef& cc,
                       TBShared<S, T, W>& s, int tx, int ty, int kk0, int kk1, const LocalGeom& geo = LocalGeom{},
-                      double rbar = 0.0)
-        : in_n(a), in_nm1(b), rho(rh), out_n(o0), out_nm1(o1), c(cc), sh(s), rb(rbar), lg(geo) {
+                      double rbar = 0.0, bool march_down = false)
+        : in_n(a), in_nm1(b), rho(rh), out_n(o0), out_nm1(o1), c(cc), sh(s), down(march_down), rb(rbar), lg(geo) {
         plane = L.plane;
         cplane = (int64_t)L.nx * L.ny;
         nz = L.nz;
@@ -187,6 +188,13 @@ struct TBTile {
             }
     }
 
+    // Plane of pipeline position p.  The pipeline runs p = k0 - T, ...,
+    // k1 + T - 1 either way; marching down reflects it onto the chunk.  The
+    // update is symmetric in its two z neighbours (their sum, or the sum of
+    // their differences, commutes exactly), so either direction gives the
+    // same bits.
+    __device__ __forceinline__ int zr(int p) const { return down ? k0 + k1 - 1 - p : p; }
+
     __device__ __forceinline__ static S at(const S* base, uint32_t off) {
         return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off);
     }
@@ -201,9 +209,10 @@ struct TBTile {
     // valid cell.
     template <int B>
     __device__ __forceinline__ void load(int p) {
-        // periodic: planes p in [k0 - T, k1 + T) wrap once when nz > T
-        const int pc = BND == TB_PERIODIC ? (nz > T ? wrap1(p, nz) : wrap(p, nz)) : min(max(p, -1), nz);
-        const int qc = BND == TB_PERIODIC ? (nz > T ? wrap1(p - 1, nz) : wrap(p - 1, nz)) : min(max(p - 1, 0), nz - 1);
+        // periodic: planes in [k0 - T, k1 + T) wrap once when nz > T
+        const int zp = zr(p), zq = zr(p - 1);
+        const int pc = BND == TB_PERIODIC ? (nz > T ? wrap1(zp, nz) : wrap(zp, nz)) : min(max(zp, -1), nz);
+        const int qc = BND == TB_PERIODIC ? (nz > T ? wrap1(zq, nz) : wrap(zq, nz)) : min(max(zq, 0), nz - 1);
         const S* bn = in_n + (int64_t)(pc + HALO) * plane;
         const S* bo = in_nm1 + (int64_t)(qc + HALO) * plane;
         const S* br = rho + (int64_t)qc * cplane;
@@ -239,14 +248,15 @@ struct TBTile {
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
             const int q = p - t;
-            // level t-1 holds plane q in MID, q+1 in NEW, q-1 in OLD; level t-2
-            // holds plane q in OLD (its NEW is q+2).  Planes outside the grid
-            // (the ghost plane and the clamped ring below and above it) keep
-            // their input value (a select on a uniform condition).
-            const bool z_in = BND == TB_PERIODIC || (q >= 0 && q < nz);
+            const int qz = zr(q);
+            // level t-1 holds pipeline position q in MID, q+1 in NEW, q-1 in
+            // OLD; level t-2 holds q in OLD (its NEW is q+2).  Planes outside
+            // the grid (the ghost plane and the clamped ring below and above
+            // it) keep their input value (a select on a uniform condition).
+            const bool z_in = BND == TB_PERIODIC || (qz >= 0 && qz < nz);
             S zz = (S)0;
             if (BND == TB_ROBIN) {
-                const S cz = local_coord<S>(lg.z0, lg.oz, lg.dx, q);
+                const S cz = local_coord<S>(lg.z0, lg.oz, lg.dx, qz);
                 zz = cz * cz;
             }
             S nv[R];
@@ -284,11 +294,13 @@ struct TBTile {
                         }
                     }
                     if (BND == TB_ROBIN) {
-                        if (q == 0 || q == nz - 1) {
-                            const S cg = q == 0 ? gz0 : gz1;
+                        if (qz == 0 || qz == nz - 1) {
+                            const S cg = qz == 0 ? gz0 : gz1;
                             const S g = robin_ghost(fma(cxi, cxi, fma(cyi[r], cyi[r], zz)),
                                                     fma(cxi, cxi, fma(cyi[r], cyi[r], cg * cg)), ce);
-                            if (q == 0)
+                            // the ghost is the neighbour below plane 0 and above
+                            // plane nz - 1: OLD going up, NEW going down
+                            if ((qz == 0) != down)
                                 zm = g;
                             else
                                 zp = g;
@@ -304,9 +316,9 @@ struct TBTile {
                 for (int r = 0; r < R; ++r) win[t][NEW][r] = nv[r];
                 sh.edge[t][SLOT][w][0][lane] = nv[0];
                 sh.edge[t][SLOT][w][1][lane] = nv[R - 1];
-            } else if (q >= k0 && q < k1) {
-                S* on = out_n + (int64_t)(q + HALO) * plane;
-                S* oo = out_nm1 + (int64_t)(q + HALO) * plane;
+            } else if (q >= k0 && q < k1) {  // the reflection keeps [k0, k1)
+                S* on = out_n + (int64_t)(qz + HALO) * plane;
+                S* oo = out_nm1 + (int64_t)(qz + HALO) * plane;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (out_ok[r]) {
@@ -374,13 +386,17 @@ __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict_
     const int xlo = tx * IX - T, ylo = ty * IY - T;
     const bool inner = xlo >= 0 && xlo + 64 <= L.nx && ylo >= 0 && ylo + W * R <= L.ny;
     const double rb = BND == TB_PERIODIC ? *rbar : 0.0;
+    // odd chunks march downwards, so two neighbouring chunks reach the planes
+    // they both read (T each side of their common face) at the same time, and
+    // the second read can find them in the last-level cache
+    const bool down = (tz & 1) != 0;
     if (inner) {
         TBTile<S, T, R, W, PF, SB, UPF, false, BND> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1, lg,
-                                                      rb);
+                                                      rb, down);
         t.run();
     } else {
         TBTile<S, T, R, W, PF, SB, UPF, true, BND> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1, lg,
-                                                     rb);
+                                                     rb, down);
         t.run();
     }
 }
