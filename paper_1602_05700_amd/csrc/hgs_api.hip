@@ -1753,6 +1753,16 @@ hgs_status hgs_destroy_batch(hgs_batch* b) {
 
 namespace {
 
+const char* bc_name(int bc) {
+    switch (bc) {
+        case HGS_BC_USER: return "user";
+        case HGS_BC_ROBIN: return "robin";
+        case HGS_BC_OUTGOING: return "outgoing";
+        case HGS_BC_PERIODIC: return "periodic";
+        default: return "multipole";
+    }
+}
+
 std::string tune_key(const hgs_config* cfg, int nsub) {
     hipDeviceProp_t p;
     int dev = 0;
@@ -1764,7 +1774,7 @@ std::string tune_key(const hgs_config* cfg, int nsub) {
     }
     std::ostringstream k;
     k << arch << ' ' << cfg->nx << ' ' << cfg->ny << ' ' << cfg->nz << ' ' << (cfg->storage == HGS_F64 ? "f64" : "f32")
-      << ' ' << nsub << ' ' << (cfg->bc == HGS_BC_USER ? "user" : "multipole");
+      << ' ' << nsub << ' ' << bc_name(cfg->bc);
     return k.str();
 }
 

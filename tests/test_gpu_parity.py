@@ -848,8 +848,12 @@ def test_autotune_and_cache(gpu_lib, tmp_path, monkeypatch):
     assert t1 is not None and cache.exists()
     b2, k2, t2 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)
     assert (b2, k2) == (b1, k1) and t2 is None  # served from the cache
+    # the boundary kind is part of the key: Robin on the same grid is timed
+    # and cached on its own line
+    t3 = gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx, bc="robin")[2]
+    assert t3 is not None and len(cache.read_text().splitlines()) == 2
     # an entry written before tiles were cached (no tile field) reads as tile 0
-    key = cache.read_text().splitlines()[-1].rsplit(" ", 2)[0]
+    key = cache.read_text().splitlines()[0].rsplit(" ", 2)[0]
     cache.write_text(f"{key} 3\n")
     assert gpu_lib.autotune(shape, rho, 1.0, 0.4 * g.dx, 4, x0=corner(shape), dx=g.dx)[:2] == (3, 0)
 
