@@ -390,7 +390,11 @@ __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict_
     // they both read (T each side of their common face) at the same time, and
     // the second read can find them in the last-level cache
     const bool down = (tz & 1) != 0;
-    if (inner) {
+    // Robin and periodic launches compile the edge body only: two bodies of
+    // the larger shapes with the boundary terms exceed the inliner's budget,
+    // and a pipeline left behind a call reaches its state through scratch
+    // memory (measured: 15 times slower)
+    if (BND == TB_FROZEN && inner) {
         TBTile<S, T, R, W, PF, SB, UPF, false, BND> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1, lg,
                                                       rb, down);
         t.run();
@@ -504,10 +508,13 @@ void launch_tblock_bnd(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S
                        const StepCoef& c, int ncu, hipStream_t st, const TBBound& b) {
     switch (b.mode) {
         case TB_ROBIN: {
-            // FP32 depth 4: shape 0 with the Robin terms exceeds the 128
-            // registers a 16-wave workgroup allows and spills; shape 1 (one
-            // plane fewer in flight) fits.  Shapes give identical results.
-            constexpr int IR = (sizeof(S) == 4 && T == 4 && I == 0) ? 1 : I;
+            // Shapes whose Robin form does not compile clean run another shape
+            // (shapes give identical results): FP32 depth 4 shape 0 spills past
+            // the 128 registers of a 16-wave workgroup and shape 2 is not
+            // inlined (its pipeline would sit behind a call, in scratch), so
+            // both run shape 1; FP32 depth 2 shape 1 spills and runs shape 0;
+            // FP64 depth 4 shape 0 is not inlined and runs shape 2.
+            constexpr int IR = sizeof(S) == 4 ? (T == 4 ? 1 : (T == 2 ? 0 : I)) : (T == 4 && I == 0 ? 2 : I);
             launch_tblock_shape<S, T, IR, TB_ROBIN>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
             break;
         }
