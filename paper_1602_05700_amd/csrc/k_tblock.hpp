@@ -445,8 +445,11 @@ inline TBlockDims tblock_dims(const Layout& L, int slots) {
 // depth's default, the fastest measured on MI355X for 512^3 FP32 and 256^3
 // FP64 (us per fused launch inside hydro steps, i.e. after the moment and
 // ghost launches):
-//   FP32 T=4: R2 W16 PF3 64-bit 777-782, R2 W16 PF2 SB 804-824,
-//             R3 W16 PF1 SB 883 (the taller tile lacks planes in flight);
+//   FP32 T=4: R2 W16 PF3 64-bit 751-782, R2 W16 PF2 SB 804-824,
+//             R2 W16 PF2 64-bit (standalone 830 against 813 for the first);
+//             taller tiles spill or lack planes in flight (R3 W16 PF1 SB 883,
+//             spilling 13 registers once the chunk direction became a
+//             run-time value, so it was replaced by the third shape);
 //   FP32 T=3 and T=2: R2 W16 PF3 64-bit 729 and 735 (SB forms 762 and 873
 //             in standalone timing against 735 and 738);
 //   FP64 T=4: R3 W8 PF1 SB 196, R2 W8 PF2 SB 257, R2 W8 PF3 64-bit 289
@@ -475,7 +478,7 @@ struct TileSet<S, 4> {
     static constexpr int N = 3;
     static constexpr TileShape at(int i) {
         return sizeof(S) == 4 ? (i == 1   ? TileShape{2, 16, 2, true, true}
-                                 : i == 2 ? TileShape{3, 16, 1, true, true}
+                                 : i == 2 ? TileShape{2, 16, 2, false, false}
                                           : TileShape{2, 16, 3, false, false})
                               : (i == 1   ? TileShape{2, 8, 3, false, false}
                                  : i == 2 ? TileShape{2, 8, 2, true, true}
