@@ -81,8 +81,9 @@ typedef enum {
      * launch as the rule's value of the neighbour's level; periodic tiles wrap
      * around the grid), with the same results as one substep per launch;
      * OUTGOING, and ROBIN or PERIODIC on a grid with an axis of one cell, run
-     * one substep per launch.  Robin ghosts are evaluated in the storage type
-     * as phi_i sqrt(r_i^2 / r_g^2).  Not available in batches. */
+     * one substep per launch.  Robin ghosts are evaluated in the storage type:
+     * FP64 as phi_i sqrt(r_i^2 / r_g^2), FP32 as phi_i r_i^2 / sqrt(r_i^2 r_g^2)
+     * with the hardware reciprocal square root.  Not available in batches. */
     HGS_BC_ROBIN = 2,     /* the paper's default outer boundary, a Robin condition amounting to
                              monopole gravity (Sec. 2, Sec. 4): r_g phi_g = r_i phi_i, i.e.
                              d(r phi)/dr = 0; exact for -G M / r */

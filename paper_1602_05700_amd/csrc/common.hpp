@@ -127,18 +127,21 @@ __device__ __forceinline__ S local_r2(S x, S y, S z) {
 
 // Robin ghost (Sec. 2, Sec. 4: a monopole far field, r phi equal at the ghost
 // and its interior neighbour) from the neighbour's value v:
-// v |x_i| / |x_g| = v sqrt(|x_i|^2 / |x_g|^2) in the storage type: FP64 with
-// the correctly rounded divide and square root; FP32 with the hardware
-// reciprocal and square root (a few ulp, far below the FP32 storage
-// rounding of the state, and a handful of instructions where the fused
-// launch evaluates it once per face cell and level).  Every kernel that sets
+// v |x_i| / |x_g| in the storage type: FP64 as v sqrt(|x_i|^2 / |x_g|^2) with
+// the correctly rounded divide and square root; FP32 as
+// v |x_i|^2 / sqrt(|x_i|^2 |x_g|^2) with the hardware reciprocal square root
+// (a few ulp, far below the FP32 storage rounding of the state, and one
+// transcendental where the fused launch evaluates it per face cell and level).  Every kernel that sets
 // or reads a Robin ghost calls this with the same operands, so streamed and
 // fused substeps agree bit for bit.
-__device__ __forceinline__ double robin_ghost(double ri2, double rg2, double v) {
-    return v * sqrt(ri2 / rg2);
+__device__ __forceinline__ double robin_ratio(double ri2, double rg2) { return sqrt(ri2 / rg2); }
+__device__ __forceinline__ float robin_ratio(float ri2, float rg2) {
+    // |x_i| / |x_g| = |x_i|^2 / sqrt(|x_i|^2 |x_g|^2): one transcendental
+    return ri2 * __builtin_amdgcn_rsqf(ri2 * rg2);
 }
-__device__ __forceinline__ float robin_ghost(float ri2, float rg2, float v) {
-    return v * __builtin_amdgcn_sqrtf(ri2 * __builtin_amdgcn_rcpf(rg2));
+template <typename S>
+__device__ __forceinline__ S robin_ghost(S ri2, S rg2, S v) {
+    return v * robin_ratio(ri2, rg2);
 }
 
 // Workgroups of one launch are handed to the 8 XCDs round-robin.  Renumber
