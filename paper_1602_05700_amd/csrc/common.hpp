@@ -144,6 +144,39 @@ __device__ __forceinline__ S robin_ghost(S ri2, S rg2, S v) {
     return v * robin_ratio(ri2, rg2);
 }
 
+// Coordinate of a face plane (cell index i, the plane at the cell's lower
+// side) along one axis, rounded to the storage type.
+template <typename S>
+__device__ __forceinline__ S local_face(double lo, double o, double dx, int i) {
+    return (S)(lo + (double)i * dx - o);
+}
+
+// Outgoing ghost (Sec. 4: the radiative form of the Robin condition,
+// d(r phi)/dt + c d(r phi)/dr = 0 with d/dr = d/dn / cos(theta) at the
+// midpoint x_f of ghost and neighbour, box scheme at t^{n+1/2}):
+//   g1 = a (g0 - b i1) + b i0,  a = (1 - al) / (1 + al),  b = r_i / r_g,
+//   al = (c dt / dx) |x_f| / s,  s = the face-normal component of x_f,
+// from the ghost's previous value g0 and the interior neighbour's previous
+// and new values i0, i1 (the form u_g' = [(1 - al) u_g + (1 + al) u_i -
+// (1 - al) u_i'] / (1 + al) with u = r phi, divided by r_g).  In the storage
+// type: FP64 with correctly rounded divides and square roots, FP32 with the
+// hardware reciprocal and reciprocal square root.  One function for the
+// ghost launch and the fused launch, so both give the same bits.
+__device__ __forceinline__ double outgoing_ghost(double ri2, double rg2, double rf2, double s, double kk,
+                                                 double g0, double i0, double i1) {
+    const double b = sqrt(ri2 / rg2);
+    const double al = kk * sqrt(rf2) / s;
+    const double a = (1.0 - al) / (1.0 + al);
+    return fma(a, fma(-b, i1, g0), b * i0);
+}
+__device__ __forceinline__ float outgoing_ghost(float ri2, float rg2, float rf2, float s, float kk, float g0,
+                                                float i0, float i1) {
+    const float b = ri2 * __builtin_amdgcn_rsqf(ri2 * rg2);
+    const float al = kk * (rf2 * __builtin_amdgcn_rsqf(rf2)) * __builtin_amdgcn_rcpf(s);
+    const float a = (1.0f - al) * __builtin_amdgcn_rcpf(1.0f + al);
+    return fmaf(a, fmaf(-b, i1, g0), b * i0);
+}
+
 // Workgroups of one launch are handed to the 8 XCDs round-robin.  Renumber
 // them so that XCD x runs a contiguous range of tiles: neighbouring tiles then
 // share that XCD's L2 for their halos.

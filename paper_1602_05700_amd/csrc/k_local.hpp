@@ -59,23 +59,20 @@ __global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int
         nxt[pg] = robin_ghost(local_r2(ci[0], ci[1], ci[2]), local_r2(cg[0], cg[1], cg[2]), nxt[pi]);
         return;
     }
-    // outgoing: the box scheme above, in FP64
-    const double lo[3] = {g.x0 - g.ox, g.y0 - g.oy, g.z0 - g.oz};
-    double xg[3], xi[3];
+    // outgoing (outgoing_ghost): positions of the ghost, the neighbour and
+    // their midpoint (the face plane along the axis)
+    const double lo[3] = {g.x0, g.y0, g.z0}, oc[3] = {g.ox, g.oy, g.oz};
+    S ci[3], cg[3], cf[3];
     for (int d = 0; d < 3; ++d) {
-        xg[d] = lo[d] + (gh[d] + 0.5) * g.dx;
-        xi[d] = lo[d] + (in[d] + 0.5) * g.dx;
+        ci[d] = local_coord<S>(lo[d], oc[d], g.dx, in[d]);
+        cg[d] = ci[d];
+        cf[d] = ci[d];
     }
-    const double rg = sqrt(xg[0] * xg[0] + xg[1] * xg[1] + xg[2] * xg[2]);
-    const double ri = sqrt(xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2]);
-    const double xf[3] = {0.5 * (xg[0] + xi[0]), 0.5 * (xg[1] + xi[1]), 0.5 * (xg[2] + xi[2])};
-    const double rf = sqrt(xf[0] * xf[0] + xf[1] * xf[1] + xf[2] * xf[2]);
-    const double cth = (hi ? xf[axis] : -xf[axis]) / rf;
-    const double al = c_dt / (g.dx * cth);
-    const double ug0 = rg * (double)cur[pg], ui0 = ri * (double)cur[pi], ui1 = ri * (double)nxt[pi];
-    const double ug1 = ((1.0 - al) * ug0 + (1.0 + al) * ui0 - (1.0 - al) * ui1) / (1.0 + al);
-    const double v = ug1 / rg;
-    nxt[pg] = (S)v;
+    cg[axis] = local_coord<S>(lo[axis], oc[axis], g.dx, gh[axis]);
+    cf[axis] = local_face<S>(lo[axis], oc[axis], g.dx, hi ? n[axis] : 0);
+    const S s = hi ? cf[axis] : -cf[axis];
+    nxt[pg] = outgoing_ghost(local_r2(ci[0], ci[1], ci[2]), local_r2(cg[0], cg[1], cg[2]),
+                             local_r2(cf[0], cf[1], cf[2]), s, (S)(c_dt / g.dx), cur[pg], cur[pi], nxt[pi]);
 }
 
 // Block-wide FP64 sum over 256 threads in a fixed order (wave butterflies,
