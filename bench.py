@@ -350,10 +350,10 @@ def run_tracking(dev, n=256, nsub=4, steps=250, every=5, omega=0.1):
 def run_next_rows(dev, n=256, nsub=4, steps=20):
     """Throughput of the parts built beyond the multipole path, at 256^3 FP32
     on the same 8-blob density (eta = 0, dt = 0.4 dx): the local boundaries
-    (at the depth and tile the autotuner picks: Robin and periodic can fuse
-    substeps, the ghosts of both new levels set after each fused launch;
-    outgoing runs one substep per launch plus a ghost launch), Robin and
-    periodic again at 512^3 with one and with four substeps per launch, the
+    (at the depth and tile the autotuner picks: all three can fuse substeps;
+    Robin and periodic ghosts of both new levels are set after each fused
+    launch, the outgoing ghosts inside it), the three again at 512^3 with one
+    and with four substeps per launch, the
     extended grid (32 vacuum
     cells on every side, outgoing boundary, rho embedded every hydro step, g on
     the hydrodynamics region; updates counted over the whole wider grid), the
@@ -393,17 +393,17 @@ def run_next_rows(dev, n=256, nsub=4, steps=20):
         best, tile, _ = hgs.autotune((n, n, n), rho, 1.0, dt, nsub, storage="f32", bc=bc, device=dev)
         sv = hgs.Solver(n, storage="f32", lmax=4, eta=0.0, bc=bc, device=dev, tblock=best, tile=tile)
         timed(bc, lambda: (sv.step(rho, 1.0, dt, nsub), sv.accel(g)), n ** 3 * nsub)
-        res[bc]["substeps_per_launch"] = 1 if bc == "outgoing" else sv.tblock
+        res[bc]["substeps_per_launch"] = sv.tblock
         res[bc]["tile"] = tile
         sv.close()
-    # Robin and periodic at 512^3, where a streamed substep is bound by HBM
+    # the local boundaries at 512^3, where a streamed substep is bound by HBM
     # (at 256^3 a field fits the last-level cache and streaming gains from
     # it): one substep per launch against four fused
     n5 = 512
     rho5 = workloads.blob_density_torch(n5, workloads.blob_params(0, 8), dev, torch.float32)
     g5 = [torch.empty((n5, n5, n5), dtype=torch.float32, device=dev) for _ in range(3)]
     dt5 = 0.4 * 2.0 / n5
-    for bc in ("robin", "periodic"):
+    for bc in ("robin", "outgoing", "periodic"):
         for T, tile in ((1, 0), (4, 1)):
             sv = hgs.Solver(n5, storage="f32", lmax=4, eta=0.0, bc=bc, device=dev, tblock=T, tile=tile)
             label = f"{bc}_512_t{T}"

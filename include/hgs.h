@@ -76,12 +76,15 @@ typedef enum {
     HGS_BC_USER = 1,      /* Dirichlet ghosts set by hgs_set_boundary and kept */
     /* Local boundaries: after every substep each face ghost g is set from the
      * interior cell i next to it (r measured from cfg.origin, which must lie
-     * strictly inside the grid).  ROBIN and PERIODIC fuse tblock substeps per
-     * launch like the frozen boundaries (Robin ghosts are taken inside the
-     * launch as the rule's value of the neighbour's level; periodic tiles wrap
-     * around the grid), with the same results as one substep per launch;
-     * OUTGOING, and ROBIN or PERIODIC on a grid with an axis of one cell, run
-     * one substep per launch.  Robin ghosts are evaluated in the storage type:
+     * strictly inside the grid).  All three fuse tblock substeps per launch
+     * like the frozen boundaries, with the same results bit for bit as one
+     * substep per launch: Robin ghosts are taken inside the launch as the
+     * rule's value of the neighbour's level, periodic tiles wrap around the
+     * grid, and outgoing ghosts are advanced level by level inside the launch
+     * (which then splits z into an even number of chunks at least tblock
+     * planes deep, so its depth is at most nz / 2).  A grid with an axis of
+     * one cell runs one substep per launch.  Robin ghosts are evaluated in the
+     * storage type:
      * FP64 as phi_i sqrt(r_i^2 / r_g^2), FP32 as phi_i r_i^2 / sqrt(r_i^2 r_g^2)
      * with the hardware reciprocal square root.  Not available in batches. */
     HGS_BC_ROBIN = 2,     /* the paper's default outer boundary, a Robin condition amounting to
@@ -497,7 +500,7 @@ const char* hgs_nn_last_error(void);
  * nsub), with HIP events for every depth 1..HGS_TMAX and every tile shape
  * compiled for it, on a temporary context built over the caller's workspace
  * (hgs_workspace_bytes(cfg) bytes; its contents are overwritten).
- * Synchronises (the OUTGOING boundary returns depth 1 without timing).
+ * Synchronises.
  * *best_tblock receives the fastest depth, *best_tile
  * (nullable) its tile index (for hgs_set_tile); ms_per_substep (nullable,
  * HGS_TMAX entries) the best measured time per substep for each depth

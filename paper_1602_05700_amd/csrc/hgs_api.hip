@@ -303,13 +303,16 @@ bool use_vec(const Layout& L) {
 // hydrodynamical step (multipole, user).
 bool local_bc(int bc) { return bc == HGS_BC_ROBIN || bc == HGS_BC_OUTGOING || bc == HGS_BC_PERIODIC; }
 
-// Substeps per launch: the fused depth, except for the outgoing rule (its
-// ghost depends on its own previous level, so every substep is a launch of
-// its own) and for Robin or periodic grids thinner than two cells (a cell
-// there borders both faces of an axis).
+// Substeps per launch: the fused depth, except for grids with a local
+// boundary thinner than two cells (a cell there borders both faces of an
+// axis), and at most nz / 2 for the outgoing rule (its fused launch splits z
+// into two or more chunks at least that deep).
 int fused_depth(const hgs_ctx* c) {
-    if (c->cfg.bc == HGS_BC_OUTGOING) return 1;
     if (local_bc(c->cfg.bc) && std::min(c->cfg.nx, std::min(c->cfg.ny, c->cfg.nz)) < 2) return 1;
+    if (c->cfg.bc == HGS_BC_OUTGOING) {
+        const int t = std::min(c->tblock, c->cfg.nz / 2);
+        return t >= 2 ? t : 1;
+    }
     return c->tblock;
 }
 
@@ -420,8 +423,11 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
     const bool local = local_bc(c->cfg.bc);
     const double* rbar = c->cfg.bc == HGS_BC_PERIODIC ? c->mean : nullptr;
     const int T = fused_depth(c);
-    const TBBound bnd{c->cfg.bc == HGS_BC_ROBIN ? TB_ROBIN : (c->cfg.bc == HGS_BC_PERIODIC ? TB_PERIODIC : TB_FROZEN),
-                      local_geom(c), c->mean};
+    const int mode = c->cfg.bc == HGS_BC_ROBIN      ? TB_ROBIN
+                     : c->cfg.bc == HGS_BC_PERIODIC ? TB_PERIODIC
+                     : c->cfg.bc == HGS_BC_OUTGOING ? TB_OUTGOING
+                                                    : TB_FROZEN;
+    const TBBound bnd{mode, local_geom(c), c->mean, c_dt};
     while (nsub > 0) {
         if (T > 1 && nsub >= T) {
             // out of place: (cur, old) -> (the other two buffers)
@@ -438,9 +444,10 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
                              c->stream, bnd);
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(5.0 * sizeof(S) * cells, cells * T);
-            if (local) {
+            if (local && mode != TB_OUTGOING) {
                 // Robin and periodic ghosts of both new levels: the rule's
-                // value from each level's own interior
+                // value from each level's own interior (the fused outgoing
+                // launch stores its ghosts itself)
                 run_local_ghosts<S>(c, o0, -1, c_dt);
                 run_local_ghosts<S>(c, o1, -1, c_dt);
             }
@@ -1817,12 +1824,6 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
     s = validate_step(nullptr, cfg, rho, c_g, dt, nsub);
     if (s != HGS_OK) return s;
     if (best_tile) *best_tile = 0;
-    if (cfg->bc == HGS_BC_OUTGOING) {  // one substep per launch: nothing to choose
-        *best_tblock = 1;
-        if (ms_per_substep)
-            for (int i = 0; i < HGS_TMAX; ++i) ms_per_substep[i] = -1.0;
-        return HGS_OK;
-    }
     const char* cache = std::getenv("HGS_TUNE_CACHE");
     const std::string key = tune_key(cfg, nsub);
     if (cache && *cache) {

@@ -31,9 +31,10 @@
 // needs a value of its own inside the launch; the launch's host then sets the
 // ghosts of both output levels by the same rule.  Periodic: there are no
 // ghosts, the tile's cells wrap around the grid (every cell is an interior
-// one), and the source is rho minus the domain mean.  Each gives the
-// streaming substeps' results bit for bit.  The outgoing rule, whose ghost
-// depends on its own previous level, stays with streaming substeps.
+// one), and the source is rho minus the domain mean.  Outgoing ghosts depend
+// on their own previous level, so they are advanced inside the launch, level
+// by level, next to the interior (TBTile below), and the launch stores them.
+// Each gives the streaming substeps' results bit for bit.
 //
 // The plane loop is unrolled by U = lcm(3, 2, T, PF) so that the three-plane
 // windows, the LDS slot parity, the ring of rho planes and the prefetch ring
@@ -70,7 +71,7 @@ struct Unroll {
     static constexpr int U = tb_lcm(tb_lcm(6, T), PF);
 };
 
-constexpr int TB_FROZEN = 0, TB_ROBIN = 1, TB_PERIODIC = 2;
+constexpr int TB_FROZEN = 0, TB_ROBIN = 1, TB_PERIODIC = 2, TB_OUTGOING = 3;
 
 __device__ __forceinline__ int wrap(int i, int n) {
     const int m = i % n;
@@ -92,7 +93,7 @@ struct TBShared {
 //     clamped loads read planes that are never used: no branch and no ring
 //     copies), else only while planes remain.
 // Which is faster depends on the shape and depth (measured; see TileSet).
-// BND: TB_FROZEN, TB_ROBIN or TB_PERIODIC (above)
+// BND: TB_FROZEN, TB_ROBIN, TB_PERIODIC or TB_OUTGOING (above)
 template <typename S, int T, int R, int W, int PF, bool SB, bool UPF, bool EDGE, int BND = TB_FROZEN>
 struct TBTile {
     static constexpr int IX = 64 - 2 * T;
@@ -108,7 +109,8 @@ struct TBTile {
     const StepCoef& c;
     TBShared<S, T, W>& sh;
     int64_t plane, cplane;  // elements per padded / compact plane
-    int nz, k0, k1;
+    int nx, ny, nz, k0, k1;
+    uint32_t prow;  // bytes per padded row
     bool down;  // march the chunk from its top plane downwards
     double rb;  // TB_PERIODIC: domain-mean density subtracted from rho
     // TB_ROBIN: which faces this thread's cells touch, the coordinates
@@ -118,6 +120,33 @@ struct TBTile {
     bool fxl, fxh, fyl[R], fyh[R];
     S cxi, cyi[R];
     S gx0, gx1, gy0, gy1, gz0, gz1;
+    // TB_OUTGOING: each face ghost follows its own rule inside the launch,
+    // g^{t} = outgoing_ghost(g^{t-1}, i^{t-1}, i^{t}) from its interior
+    // neighbour i along the normal.
+    //   x ghosts are lanes: updated in place, the neighbour's two levels by
+    //     lane shifts.
+    //   y ghosts: the thread holding the row y = 0 (ny - 1) keeps the ghost
+    //     row's levels beside it in registers (one per level) and reads its y
+    //     neighbour from there, so no level of a ghost row crosses a wave; the
+    //     ghost rows themselves are never read otherwise.
+    //   z ghosts: the launch has an even number of z chunks, at least T planes
+    //     deep, so the bottom chunk marches up and the top one down, a grid's
+    //     ghost plane is always the plane before its chunk in marching order,
+    //     and no chunk's halo reaches the other one.  Its level t is
+    //     set one step late, when plane k0's level t exists and before any
+    //     cell reads it (pipeline iteration T + t, a compile-time phase).
+    // The launch stores the face ghosts of both new levels (edges and corners
+    // are never read).
+    S okk;                  // c dt / dx
+    bool oxg[R], oxs[R];    // x-face ghost (y inside the grid); stored by this tile
+    bool oxw;               // the tile reaches an x face (the same in the whole workgroup)
+    bool oxlo;              // the lane is at x = -1 (else x = nx)
+    S ocx;                  // x of the cell
+    S ocy[R];               // y of the cells
+    int oyl, oyh;           // row of this thread at y = 0 / y = ny - 1, or -1
+    bool osl, osh;          // ... whose ghost this tile stores
+    S gyl[T], gyh[T];       // level t of the y ghosts beside those rows (1 <= t < T)
+    bool ozb;               // the plane before the chunk is a ghost
     // per-thread constants.  Addresses are a uniform plane base plus a 32-bit
     // byte offset, so loads and stores take the scalar-base form and need no
     // per-access 64-bit address arithmetic.
@@ -131,13 +160,19 @@ struct TBTile {
     S rq[T][R];      // ring of rho planes
     S pn[PF][R], po[PF][R], pr[PF][R];  // prefetch ring
 
-    __device__ TBTile(const S* a, const S* b, const S* rh, S* o0, S* o1, const Layout& L, const StepCoef& cc,
-                      TBShared<S, T, W>& s, int tx, int ty, int kk0, int kk1, const LocalGeom& geo = LocalGeom{},
-                      double rbar = 0.0, bool march_down = false)
+    // always inlined: a constructor left behind a call takes the address of
+    // the whole tile, whose pipeline state then lives in scratch memory
+    __device__ __forceinline__ TBTile(const S* a, const S* b, const S* rh, S* o0, S* o1, const Layout& L, const StepCoef& cc,
+                      TBShared<S, T, W>& s, int tx, int ty, int kk0, int kk1,
+                      const LocalGeom& geo = LocalGeom{}, double rbar = 0.0, bool march_down = false,
+                      double c_dt = 0.0)
         : in_n(a), in_nm1(b), rho(rh), out_n(o0), out_nm1(o1), c(cc), sh(s), down(march_down), rb(rbar), lg(geo) {
         plane = L.plane;
         cplane = (int64_t)L.nx * L.ny;
+        nx = L.nx;
+        ny = L.ny;
         nz = L.nz;
+        prow = (uint32_t)(L.pitch * (int)sizeof(S));
         lane = threadIdx.x & 63;
         w = threadIdx.x >> 6;
         const int x = tx * IX - T + lane;
@@ -162,6 +197,16 @@ struct TBTile {
             gz0 = local_coord<S>(lg.z0, lg.oz, lg.dx, -1);
             gz1 = local_coord<S>(lg.z0, lg.oz, lg.dx, L.nz);
         }
+        if (BND == TB_OUTGOING) {
+            okk = (S)(c_dt / lg.dx);
+            const int xlo = tx * IX - T;
+            oxw = xlo < 0 || xlo + 64 > L.nx;
+            oxlo = x == -1;
+            ocx = local_coord<S>(lg.x0, lg.ox, lg.dx, x);
+            oyl = oyh = -1;
+            osl = osh = false;
+            ozb = down ? k1 == L.nz : k0 == 0;
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = y0 + r;
@@ -178,6 +223,20 @@ struct TBTile {
                 fyh[r] = y == L.ny - 1;
                 cyi[r] = local_coord<S>(lg.y0, lg.oy, lg.dx, y);
             }
+            if (BND == TB_OUTGOING) {
+                const int ln = x == -1 ? lane + 1 : lane - 1;  // the x ghost's neighbour lane
+                oxg[r] = (x == -1 || x == L.nx) && y_in;
+                oxs[r] = oxg[r] && ln >= T && ln < T + IX && er >= T && er < T + IY;
+                ocy[r] = local_coord<S>(lg.y0, lg.oy, lg.dx, y);
+                if (y == 0) {
+                    oyl = r;
+                    osl = out_ok[r];
+                }
+                if (y == L.ny - 1) {
+                    oyh = r;
+                    osh = out_ok[r];
+                }
+            }
         }
 #pragma unroll
         for (int t = 0; t < T; ++t)
@@ -186,6 +245,9 @@ struct TBTile {
                 win[t][0][r] = win[t][1][r] = win[t][2][r] = (S)0;
                 rq[t][r] = (S)0;
             }
+        if (BND == TB_OUTGOING)
+#pragma unroll
+            for (int t = 0; t < T; ++t) gyl[t] = gyh[t] = (S)0;
     }
 
     // Plane of pipeline position p.  The pipeline runs p = k0 - T, ...,
@@ -245,6 +307,7 @@ struct TBTile {
         __syncthreads();  // LDS writes of plane p-1 are visible; its reads are done
         sh.edge[0][SLOT][w][0][lane] = win[0][NEW][0];
         sh.edge[0][SLOT][w][1][lane] = win[0][NEW][R - 1];
+        S cl = (S)0, ch = (S)0;  // TB_OUTGOING: level t-1 of the y ghosts at plane q (t >= 2)
 #pragma unroll
         for (int t = 1; t <= T; ++t) {
             const int q = p - t;
@@ -260,6 +323,10 @@ struct TBTile {
                 zz = cz * cz;
             }
             S nv[R];
+            // TB_OUTGOING: the y ghosts' level t-1 at plane q (the input at
+            // t = 1, then the registers kept beside rows oyl / oyh), and the
+            // levels t-1 and t of those rows
+            S gl = (S)0, gh = (S)0, il = (S)0, ih = (S)0, nl = (S)0, nh = (S)0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const S ce = win[t - 1][MID][r];
@@ -306,11 +373,98 @@ struct TBTile {
                                 zp = g;
                         }
                     }
+                    if (BND == TB_OUTGOING) {
+                        if (r == oyl) {
+                            if (t >= 2) ym = cl;
+                            gl = ym;
+                            il = ce;
+                        }
+                        if (r == oyh) {
+                            if (t >= 2) yp = ch;
+                            gh = yp;
+                            ih = ce;
+                        }
+                    }
                     const S ol = (t == 1) ? old1[r] : win[t >= 2 ? t - 2 : 0][OLD][r];
                     const int RS = ((PH - t + 1) % T + T) % T;  // ring slot of rho(p - t)
                     const S v = (S)update(c, ce, xm, xp, ym, yp, zm, zp, ol, rq[RS][r]);
                     nv[r] = (EDGE ? (in_ok[r] && z_in) : z_in) ? v : ce;
+                    if (BND == TB_OUTGOING && oxw) {
+                        // x ghosts in place: the neighbour lane's levels t-1
+                        // (xp / xm) and t (shifted here by every lane)
+                        const S nn = (S)lane_next(nv[r]), np = (S)lane_prev(nv[r]);
+                        if (oxg[r] && z_in) {
+                            const S cz = local_coord<S>(lg.z0, lg.oz, lg.dx, qz);
+                            const S yz = fma(ocy[r], ocy[r], cz * cz);
+                            const S xn = local_coord<S>(lg.x0, lg.ox, lg.dx, oxlo ? 0 : nx - 1);
+                            const S xf = local_face<S>(lg.x0, lg.ox, lg.dx, oxlo ? 0 : nx);
+                            nv[r] = outgoing_ghost(fma(xn, xn, yz), fma(ocx, ocx, yz), fma(xf, xf, yz),
+                                                   oxlo ? -xf : xf, okk, ce, oxlo ? xp : xm, oxlo ? nn : np);
+                        }
+                    }
+                    if (BND == TB_OUTGOING) {
+                        if (r == oyl) nl = nv[r];
+                        if (r == oyh) nh = nv[r];
+                    }
                 }
+            // TB_OUTGOING: y ghosts beside rows oyl / oyh, and the z ghost planes
+            S Gl = (S)0, Gh = (S)0;
+            if (BND == TB_OUTGOING) {
+                if (oyl >= 0 || oyh >= 0) {
+                    const S cz = local_coord<S>(lg.z0, lg.oz, lg.dx, qz);
+                    if (oyl >= 0) {
+                        const S yf = local_face<S>(lg.y0, lg.oy, lg.dx, 0);
+                        Gl = outgoing_ghost(local_r2(ocx, local_coord<S>(lg.y0, lg.oy, lg.dx, 0), cz),
+                                            local_r2(ocx, local_coord<S>(lg.y0, lg.oy, lg.dx, -1), cz),
+                                            local_r2(ocx, yf, cz), -yf, okk, gl, il, nl);
+                    }
+                    if (oyh >= 0) {
+                        const S yf = local_face<S>(lg.y0, lg.oy, lg.dx, ny);
+                        Gh = outgoing_ghost(local_r2(ocx, local_coord<S>(lg.y0, lg.oy, lg.dx, ny - 1), cz),
+                                            local_r2(ocx, local_coord<S>(lg.y0, lg.oy, lg.dx, ny), cz),
+                                            local_r2(ocx, yf, cz), yf, okk, gh, ih, nh);
+                    }
+                    if (t < T) {
+                        // level t+1 (plane q - 1) reads level t of plane q - 1
+                        cl = gyl[t];
+                        ch = gyh[t];
+                        gyl[t] = Gl;
+                        gyh[t] = Gh;
+                    }
+                }
+                // the plane before the chunk: level t from plane k0's levels
+                // t-1 and t (its own level t-1 is level t-1's OLD plane);
+                // level t reaches plane k0 at iteration T + t
+                if ((T + t) % U == PH && ozb && q == k0) {
+                    const int zg = zr(k0 - 1), zi = zr(k0);
+                    const bool hi = zg >= 0;
+                    const S czi = local_coord<S>(lg.z0, lg.oz, lg.dx, zi), czg = local_coord<S>(lg.z0, lg.oz, lg.dx, zg),
+                            czf = local_face<S>(lg.z0, lg.oz, lg.dx, hi ? nz : 0);
+                    S g[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        g[r] = outgoing_ghost(local_r2(ocx, ocy[r], czi), local_r2(ocx, ocy[r], czg),
+                                              local_r2(ocx, ocy[r], czf), hi ? czf : -czf, okk,
+                                              win[t - 1][OLD][r], win[t - 1][MID][r], nv[r]);
+                    }
+                    if (t < T) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if (in_ok[r]) win[t][MID][r] = g[r];
+                    } else {
+                        S* on = out_n + (int64_t)(zg + HALO) * plane;
+                        S* oo = out_nm1 + (int64_t)(zg + HALO) * plane;
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if (out_ok[r]) {
+                                uint32_t o = bp[r];
+                                if (SB) asm("" : "+v"(o));
+                                put(on, o, g[r]);
+                                put(oo, o, win[T - 1][OLD][r]);
+                            }
+                    }
+                }
+            }
             if (t < T) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) win[t][NEW][r] = nv[r];
@@ -321,13 +475,29 @@ struct TBTile {
                 S* oo = out_nm1 + (int64_t)(qz + HALO) * plane;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    if (out_ok[r]) {
+                    // TB_OUTGOING: x ghost lanes store their own levels too
+                    if (out_ok[r] || (BND == TB_OUTGOING && oxs[r])) {
                         uint32_t o = bp[r];
                         // SB: keep the 32-bit offset in this block so the
                         // stores take the scalar-base form like the loads
                         if (SB) asm("" : "+v"(o));
                         put(on, o, nv[r]);
                         put(oo, o, win[T - 1][MID][r]);
+                    }
+                }
+                if (BND == TB_OUTGOING) {
+                    // the y ghosts beside rows oyl / oyh (level T-1 is the
+                    // value their rows read at level T)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r == oyl && osl) {
+                            put(on, bp[r] - prow, Gl);
+                            put(oo, bp[r] - prow, gl);
+                        }
+                        if (r == oyh && osh) {
+                            put(on, bp[r] + prow, Gh);
+                            put(oo, bp[r] + prow, gh);
+                        }
                     }
                 }
             }
@@ -359,16 +529,24 @@ struct TBTile {
         for (int p = k0 - T; p < pend; p += U)
             if (!run_from<0>(p, pend)) break;
     }
+    // the same, always inlined (for bodies the inliner would leave behind a
+    // call, whose pipeline state would then live in scratch memory)
+    __device__ __forceinline__ void run_inline() {
+        const int pend = k1 + T;
+        prime<0>(k0 - T);
+        for (int p = k0 - T; p < pend; p += U)
+            if (!run_from<0>(p, pend)) break;
+    }
 };
 
-// BND: TB_FROZEN, TB_ROBIN (lg: cell positions) or TB_PERIODIC (rbar: device
-// pointer to the domain-mean density)
+// BND: TB_FROZEN, TB_ROBIN (lg: cell positions), TB_PERIODIC (rbar: device
+// pointer to the domain-mean density) or TB_OUTGOING (lg, and c_dt = c_g dt)
 template <typename S, int T, int R, int W, int PF, bool SB, bool UPF, int BND>
 __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict__ in_n, const S* __restrict__ in_nm1,
                                                             const S* __restrict__ rho, S* __restrict__ out_n,
                                                             S* __restrict__ out_nm1, Layout L, StepCoef c, int zc,
                                                             int tiles_x, int tiles_y, LocalGeom lg,
-                                                            const double* __restrict__ rbar) {
+                                                            const double* __restrict__ rbar, double c_dt) {
     constexpr int IX = 64 - 2 * T;
     constexpr int IY = W * R - 2 * T;
     static_assert(IX > 0 && IY > 0, "tile too small for the temporal depth");
@@ -390,18 +568,21 @@ __global__ __launch_bounds__(64 * W) void k_leapfrog_tblock(const S* __restrict_
     // they both read (T each side of their common face) at the same time, and
     // the second read can find them in the last-level cache
     const bool down = (tz & 1) != 0;
-    // Robin and periodic launches compile the edge body only: two bodies of
+    // Local-boundary launches compile the edge body only: two bodies of
     // the larger shapes with the boundary terms exceed the inliner's budget,
     // and a pipeline left behind a call reaches its state through scratch
     // memory (measured: 15 times slower)
     if (BND == TB_FROZEN && inner) {
         TBTile<S, T, R, W, PF, SB, UPF, false, BND> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1, lg,
-                                                      rb, down);
+                                                      rb, down, c_dt);
         t.run();
     } else {
         TBTile<S, T, R, W, PF, SB, UPF, true, BND> t(in_n, in_nm1, rho, out_n, out_nm1, L, c, sh, tx, ty, k0, k1, lg,
-                                                     rb, down);
-        t.run();
+                                                     rb, down, c_dt);
+        if (BND == TB_OUTGOING)
+            t.run_inline();
+        else
+            t.run();
     }
 }
 
@@ -412,9 +593,12 @@ struct TBlockDims {
 
 // Number of z chunks: each workgroup occupies one CU slot for (chunk planes +
 // 2T) pipeline steps and the launch runs in ceil(blocks / slots) rounds, so
-// pick the chunk count that minimises rounds x steps.
+// pick the chunk count that minimises rounds x steps.  even: only even counts
+// of chunks at least T planes deep (needs nz >= 2T), so that the bottom chunk
+// marches up and the top one down, and no chunk's T-plane halo reaches a
+// ghost plane other than the one before it (the outgoing form's ghost planes).
 template <int T, int R, int W>
-inline TBlockDims tblock_dims(const Layout& L, int slots) {
+inline TBlockDims tblock_dims(const Layout& L, int slots, bool even = false) {
     constexpr int IX = 64 - 2 * T;
     constexpr int IY = W * R - 2 * T;
     TBlockDims d;
@@ -423,10 +607,12 @@ inline TBlockDims tblock_dims(const Layout& L, int slots) {
     const int64_t cols = (int64_t)d.tiles_x * d.tiles_y;
     int best = 1;
     int64_t best_cost = -1;
-    const int maxz = std::max(1, std::min(64, L.nz / (2 * T)));
+    const int maxz = std::max(even ? 2 : 1, std::min(64, L.nz / (2 * T)));
     for (int nzc = 1; nzc <= maxz; ++nzc) {
         const int zc = (L.nz + nzc - 1) / nzc;
-        const int64_t nb = cols * ((L.nz + zc - 1) / zc);
+        const int nch = (L.nz + zc - 1) / zc;
+        if (even && (nch % 2 != 0 || zc < T || L.nz - (nch - 1) * zc < T)) continue;
+        const int64_t nb = cols * nch;
         const int64_t cost = ((nb + slots - 1) / slots) * (int64_t)(zc + 2 * T);
         if (best_cost < 0 || cost < best_cost) {
             best_cost = cost;
@@ -488,22 +674,23 @@ struct TileSet<S, 4> {
 
 inline int tile_count(int T) { return T == 4 ? 3 : (T >= 2 ? 2 : 1); }
 
-// Outer boundary of a fused launch: mode (TB_*), cell positions (Robin) and
-// the device mean density (periodic)
+// Outer boundary of a fused launch: mode (TB_*), cell positions (Robin,
+// outgoing), the device mean density (periodic) and c_g dt (outgoing)
 struct TBBound {
     int mode;
     LocalGeom lg;
     const double* rbar;
+    double c_dt;
 };
 
 template <typename S, int T, int I, int BND>
 void launch_tblock_shape(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
                          const StepCoef& c, int ncu, hipStream_t st, const TBBound& b) {
     constexpr TileShape sh = TileSet<S, T>::at(I);
-    const TBlockDims d = tblock_dims<T, sh.R, sh.W>(L, ncu);
+    const TBlockDims d = tblock_dims<T, sh.R, sh.W>(L, ncu, BND == TB_OUTGOING);
     hipLaunchKernelGGL((k_leapfrog_tblock<S, T, sh.R, sh.W, sh.PF, sh.SB, sh.UPF, BND>), dim3(d.nblocks),
                        dim3(64 * sh.W), 0, st, in_n, in_nm1, rho, out_n, out_nm1, L, c, d.zc, d.tiles_x, d.tiles_y,
-                       b.lg, b.rbar);
+                       b.lg, b.rbar, b.c_dt);
 }
 
 template <typename S, int T, int I>
@@ -524,6 +711,14 @@ void launch_tblock_bnd(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S
         case TB_PERIODIC:
             launch_tblock_shape<S, T, I, TB_PERIODIC>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
             break;
+        case TB_OUTGOING: {
+            // The same for the outgoing form: FP32 depth 4 runs shape 1 (the
+            // others spill), FP32 depths 2 and 3 shape 0 (shape 1 spills),
+            // FP64 depth 4 shape 2 (the others spill).
+            constexpr int IO = sizeof(S) == 4 ? (T == 4 ? 1 : 0) : (T == 4 ? 2 : I);
+            launch_tblock_shape<S, T, IO, TB_OUTGOING>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
+            break;
+        }
         default: launch_tblock_shape<S, T, I, TB_FROZEN>(in_n, in_nm1, rho, out_n, out_nm1, L, c, ncu, st, b);
     }
 }
@@ -546,7 +741,7 @@ void launch_tblock_t(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* 
 template <typename S>
 void launch_tblock(const S* in_n, const S* in_nm1, const S* rho, S* out_n, S* out_nm1, const Layout& L,
                    const StepCoef& c, int T, int tile, int ncu, hipStream_t st,
-                   const TBBound& b = TBBound{TB_FROZEN, LocalGeom{}, nullptr}) {
+                   const TBBound& b = TBBound{TB_FROZEN, LocalGeom{}, nullptr, 0.0}) {
     switch (T) {
         case 2: launch_tblock_t<S, 2>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st, b); break;
         case 3: launch_tblock_t<S, 3>(in_n, in_nm1, rho, out_n, out_nm1, L, c, tile, ncu, st, b); break;

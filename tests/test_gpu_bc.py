@@ -141,32 +141,31 @@ def test_outgoing_checkpoint_bitwise(gpu_lib, storage):
 
 
 def test_local_bc_rejected_in_batch_and_tuned(gpu_lib):
-    """Local boundaries are refused in batches; the autotuner returns depth 1
-    for the outgoing rule without timing and times every depth for Robin and
-    periodic, which fuse substeps."""
+    """Local boundaries are refused in batches; the autotuner times every
+    depth and tile for each of them (all three fuse substeps)."""
     hgs = gpu_lib
     with pytest.raises(hgs.HGSError):
         hgs.Batch([16, 32], bc="robin", storage="f32", device="cuda")
     rho = to_dev(dens((16, 16, 16), 27, "f32"))
-    best, tile, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc="outgoing",
-                                     device="cuda")
-    assert best == 1 and tile == 0 and times is None
-    for bc in ("robin", "periodic"):
+    for bc in LOCAL:
         best, tile, times = hgs.autotune((16, 16, 16), rho, 1.0, 0.4 * 2.0 / 16, 4, storage="f32", bc=bc,
                                          device="cuda")
         assert 1 <= best <= 4 and 0 <= tile < max(1, hgs.tile_count(best)) and all(t > 0 for t in times)
 
 
-@pytest.mark.parametrize("bc", ["robin", "periodic"])
+@pytest.mark.parametrize("bc", LOCAL)
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("shape", [(2, 2, 2), (7, 9, 5), (23, 29, 37), (40, 33, 130), (70, 61, 66), (9, 150, 67)])
+@pytest.mark.parametrize("shape", [(2, 2, 2), (3, 2, 4), (7, 9, 5), (23, 29, 37), (40, 33, 130), (70, 61, 66),
+                                   (9, 150, 67)])
 @pytest.mark.parametrize("T,tile", [(4, 0), (4, 1), (4, 2), (3, 0), (3, 1), (2, 0), (2, 1)])
 def test_fused_local_bc_bitwise_equals_streaming(gpu_lib, bc, storage, shape, T, tile):
-    """Robin and periodic substeps fused T per launch give the streaming
-    results bit for bit: the potential, phi^{n-1}, the ghost faces and g,
-    over hydro steps whose substep counts are and are not multiples of T,
-    with a dt change (phi^{n-1} rescaled), on grids smaller than one tile,
-    with ragged tiles in every direction, and more tiles in y than in x."""
+    """Robin, outgoing and periodic substeps fused T per launch give the
+    streaming results bit for bit: the potential, phi^{n-1}, the ghost faces
+    and g, over hydro steps whose substep counts are and are not multiples of
+    T, with a dt change (phi^{n-1} rescaled), on grids smaller than one tile,
+    with ragged tiles in every direction, and more tiles in y than in x.  The
+    outgoing ghosts carry their own state from launch to launch, so a wrong
+    ghost level anywhere inside a fused launch shows in the faces."""
     import torch
 
     g = grid_of(shape)
@@ -185,7 +184,7 @@ def test_fused_local_bc_bitwise_equals_streaming(gpu_lib, bc, storage, shape, T,
     assert all(torch.equal(u, v) for u, v in zip(a.accel(), b.accel()))
 
 
-@pytest.mark.parametrize("bc", ["robin", "periodic"])
+@pytest.mark.parametrize("bc", LOCAL)
 def test_fused_local_bc_against_oracle_256(gpu_lib, bc):
     """At 256^3 FP32 (fused depth 4, the launch the bench times for these
     boundaries) two hydro steps against the FP64 oracle at the FP32 bar."""
