@@ -444,37 +444,49 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
                              c->stream, bnd);
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(5.0 * sizeof(S) * cells, cells * T);
-            if (local && mode != TB_OUTGOING) {
-                // Robin and periodic ghosts of both new levels: the rule's
-                // value from each level's own interior (the fused outgoing
-                // launch stores its ghosts itself)
-                run_local_ghosts<S>(c, o0, -1, c_dt);
-                run_local_ghosts<S>(c, o1, -1, c_dt);
-            }
+            // periodic ghosts of the new phi^n (a streaming substep after it
+            // reads them; phi^{n-1}'s ghosts are never read: the next substep
+            // writes its new level over them and sets them again); Robin
+            // ghosts are set once at the end; the fused outgoing launch stores
+            // its ghosts itself
+            if (mode == TB_PERIODIC) run_local_ghosts<S>(c, o0, -1, c_dt);
             c->cur = o0;
             c->old = o1;
             nsub -= T;
         } else {
             int zc, tx, ty, nb;
             Timed tm(c, HGS_KERNEL_STENCIL);
+            const LocalGeom lg = local_geom(c);
             if (use_vec<S>(c->L)) {
                 stream_dims(c->L, 64 * Vec16<S>::N, zc, tx, ty, nb);
-                hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream,
-                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar);
+                if (mode == TB_ROBIN)
+                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY, true>), dim3(nb), dim3(64, SBY), 0, c->stream,
+                                       B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
+                else
+                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream,
+                                       B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
             } else {
                 stream_dims(c->L, SBX, zc, tx, ty, nb);
-                hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream,
-                                   B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar);
+                if (mode == TB_ROBIN)
+                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY, true>), dim3(nb), dim3(SBX, SBY), 0,
+                                       c->stream, B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
+                else
+                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream,
+                                       B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
             }
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(4.0 * sizeof(S) * cells, cells);
             // the new level (written over phi^{n-1}) gets its ghosts from its
-            // interior and, for the outgoing rule, from phi^n
-            if (local) run_local_ghosts<S>(c, c->old, c->cur, c_dt);
+            // interior and, for the outgoing rule, from phi^n (Robin substeps
+            // evaluate their ghosts where they read them: set at the end)
+            if (local && mode != TB_ROBIN) run_local_ghosts<S>(c, c->old, c->cur, c_dt);
             std::swap(c->cur, c->old);
             nsub -= 1;
         }
     }
+    // Robin: the substeps evaluate their ghosts where they read them; phi^n's
+    // ghost layer is set once, for the gradient, the residual and the faces
+    if (mode == TB_ROBIN) run_local_ghosts<S>(c, c->cur, -1, c_dt);
 }
 
 // Gradient over the cells of layout W read from phi (W may be a box inside

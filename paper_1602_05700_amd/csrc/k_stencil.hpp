@@ -13,14 +13,26 @@
 
 namespace hgs {
 
+// The Robin ghost beside a face cell, evaluated where it is read: the rule's
+// value from the cell's own value v, with the ghost at the cell's position
+// moved past the face, (gx, gy, gz).  These are the operands the ghost launch
+// uses, so the result equals the stored ghost bit for bit, and a substep that
+// evaluates its Robin ghosts this way needs no ghost launch before it.
+template <typename S>
+__device__ __forceinline__ S robin_beside(S x, S y, S z, S gx, S gy, S gz, S v) {
+    return robin_ghost(local_r2(x, y, z), local_r2(gx, gy, gz), v);
+}
+
 // rbar (nullable, device): density subtracted from rho in the source, the
 // domain mean on a periodic grid; rho - 0 = rho exactly, so results without it
-// are bit-identical to the fused kernels.
-template <typename S, int BX, int BY>
+// are bit-identical to the fused kernels.  ROBIN: the face cells evaluate
+// their Robin ghosts (robin_beside; lg: cell positions) instead of reading
+// the ghost layer.
+template <typename S, int BX, int BY, bool ROBIN = false>
 __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict__ cur, S* __restrict__ old_new,
                                                             const S* __restrict__ rho, Layout L, StepCoef c,
                                                             int zc, int tiles_x, int tiles_y,
-                                                            const double* __restrict__ rbar) {
+                                                            const double* __restrict__ rbar, LocalGeom lg) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = bid % tiles_x;
     const int ty = (bid / tiles_x) % tiles_y;
@@ -42,11 +54,22 @@ __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict_
     S z0 = pc[0];
     for (int k = k0; k < k1; ++k) {
         const S zp = pc[plane];
-        const S xm = pc[-1], xp = pc[1];
-        const S ym = pc[-pitch], yp = pc[pitch];
+        S xm = pc[-1], xp = pc[1];
+        S ym = pc[-pitch], yp = pc[pitch];
+        S zmu = zm, zpu = zp;
+        if (ROBIN && (i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1 || k == 0 || k == L.nz - 1)) {
+            const S cx = local_coord<S>(lg.x0, lg.ox, lg.dx, i), cy = local_coord<S>(lg.y0, lg.oy, lg.dx, j),
+                    cz = local_coord<S>(lg.z0, lg.oz, lg.dx, k);
+            if (i == 0) xm = robin_beside(cx, cy, cz, local_coord<S>(lg.x0, lg.ox, lg.dx, -1), cy, cz, z0);
+            if (i == L.nx - 1) xp = robin_beside(cx, cy, cz, local_coord<S>(lg.x0, lg.ox, lg.dx, L.nx), cy, cz, z0);
+            if (j == 0) ym = robin_beside(cx, cy, cz, cx, local_coord<S>(lg.y0, lg.oy, lg.dx, -1), cz, z0);
+            if (j == L.ny - 1) yp = robin_beside(cx, cy, cz, cx, local_coord<S>(lg.y0, lg.oy, lg.dx, L.ny), cz, z0);
+            if (k == 0) zmu = robin_beside(cx, cy, cz, cx, cy, local_coord<S>(lg.z0, lg.oz, lg.dx, -1), z0);
+            if (k == L.nz - 1) zpu = robin_beside(cx, cy, cz, cx, cy, local_coord<S>(lg.z0, lg.oz, lg.dx, L.nz), z0);
+        }
         const S o = *po;
         const S r = source(*pr, rb);
-        *po = (S)update(c, z0, xm, xp, ym, yp, zm, zp, o, r);
+        *po = (S)update(c, z0, xm, xp, ym, yp, zmu, zpu, o, r);
         zm = z0;
         z0 = zp;
         pc += plane;
@@ -169,11 +192,11 @@ __device__ __forceinline__ VLane vlane(const Layout& L, int tx, int ty, int BY) 
 }
 
 // One (64N x BY) column tile, planes [k0, k1): the body shared by the
-// single-grid and the batched launches.
-template <typename S, int BY>
+// single-grid and the batched launches.  ROBIN as in k_leapfrog_stream.
+template <typename S, int BY, bool ROBIN = false>
 __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __restrict__ old_new,
                                               const S* __restrict__ rho, const Layout& L, const StepCoef& c, int tx,
-                                              int ty, int k0, int k1, double rb) {
+                                              int ty, int k0, int k1, double rb, const LocalGeom& lg = LocalGeom{}) {
     using V = Vec16<S>;
     using VT = typename V::T;
     constexpr int N = V::N;
@@ -198,13 +221,36 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
         S right = from_next(V::get(z0, 0));
         if (lane == 0) left = pc[-1];
         if (lane == 63) right = pc[N];
+        // ROBIN: the row (y) and the plane (z) are the same for the whole wave
+        const bool yzface = ROBIN && (g.j == 0 || g.j == L.ny - 1 || k == 0 || k == L.nz - 1);
+        S cy = (S)0, cz = (S)0;
+        if (ROBIN) {
+            cy = local_coord<S>(lg.y0, lg.oy, lg.dx, g.j);
+            cz = local_coord<S>(lg.z0, lg.oz, lg.dx, k);
+            if (g.i0 == 0)
+                left = robin_beside(local_coord<S>(lg.x0, lg.ox, lg.dx, 0), cy, cz,
+                                    local_coord<S>(lg.x0, lg.ox, lg.dx, -1), cy, cz, (S)V::get(z0, 0));
+            if (g.i0 + N == L.nx)
+                right = robin_beside(local_coord<S>(lg.x0, lg.ox, lg.dx, L.nx - 1), cy, cz,
+                                     local_coord<S>(lg.x0, lg.ox, lg.dx, L.nx), cy, cz, (S)V::get(z0, N - 1));
+        }
         VT out;
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const S xm = n > 0 ? (S)V::get(z0, n - 1) : left;
             const S xp = n < N - 1 ? (S)V::get(z0, n + 1) : right;
-            const S v = (S)update(c, (S)V::get(z0, n), xm, xp, (S)V::get(ym, n), (S)V::get(yp, n),
-                                  (S)V::get(zm, n), (S)V::get(zp, n), (S)V::get(o, n), source((S)V::get(r, n), rb));
+            S ymn = (S)V::get(ym, n), ypn = (S)V::get(yp, n), zmn = (S)V::get(zm, n), zpn = (S)V::get(zp, n);
+            if (yzface) {
+                const S cx = local_coord<S>(lg.x0, lg.ox, lg.dx, g.i0 + n), ce = (S)V::get(z0, n);
+                if (g.j == 0) ymn = robin_beside(cx, cy, cz, cx, local_coord<S>(lg.y0, lg.oy, lg.dx, -1), cz, ce);
+                if (g.j == L.ny - 1)
+                    ypn = robin_beside(cx, cy, cz, cx, local_coord<S>(lg.y0, lg.oy, lg.dx, L.ny), cz, ce);
+                if (k == 0) zmn = robin_beside(cx, cy, cz, cx, cy, local_coord<S>(lg.z0, lg.oz, lg.dx, -1), ce);
+                if (k == L.nz - 1)
+                    zpn = robin_beside(cx, cy, cz, cx, cy, local_coord<S>(lg.z0, lg.oz, lg.dx, L.nz), ce);
+            }
+            const S v = (S)update(c, (S)V::get(z0, n), xm, xp, ymn, ypn, zmn, zpn, (S)V::get(o, n),
+                                  source((S)V::get(r, n), rb));
             V::set(out, n, v);
         }
         if (g.active) *reinterpret_cast<VT*>(po) = out;
@@ -216,17 +262,17 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
     }
 }
 
-template <typename S, int BY>
+template <typename S, int BY, bool ROBIN = false>
 __global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restrict__ cur, S* __restrict__ old_new,
                                                                const S* __restrict__ rho, Layout L, StepCoef c, int zc,
                                                                int tiles_x, int tiles_y,
-                                                               const double* __restrict__ rbar) {
+                                                               const double* __restrict__ rbar, LocalGeom lg) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = bid % tiles_x;
     const int ty = (bid / tiles_x) % tiles_y;
     const int tz = bid / (tiles_x * tiles_y);
     const int k0 = tz * zc;
-    stream_v_tile<S, BY>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz), rbar ? *rbar : 0.0);
+    stream_v_tile<S, BY, ROBIN>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz), rbar ? *rbar : 0.0, lg);
 }
 
 // Central-difference gradient, 16 bytes per lane along x, R rows per thread:
