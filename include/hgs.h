@@ -86,7 +86,10 @@ typedef enum {
      * one cell runs one substep per launch.  Robin ghosts are evaluated in the
      * storage type:
      * FP64 as phi_i sqrt(r_i^2 / r_g^2), FP32 as phi_i r_i^2 / sqrt(r_i^2 r_g^2)
-     * with the hardware reciprocal square root.  Not available in batches. */
+     * with the hardware reciprocal square root.  Substeps evaluate or advance
+     * the ghosts they need themselves; the ghost layer of phi^n is the rule's
+     * after every hgs_step (hgs_get_boundary, the gradient, the residual).
+     * Not available in batches. */
     HGS_BC_ROBIN = 2,     /* the paper's default outer boundary, a Robin condition amounting to
                              monopole gravity (Sec. 2, Sec. 4): r_g phi_g = r_i phi_i, i.e.
                              d(r phi)/dr = 0; exact for -G M / r */
@@ -498,7 +501,8 @@ const char* hgs_nn_last_error(void);
  * Picks the fused depth (substeps per stencil launch) and the tile shape for a
  * configuration by timing whole hydrodynamical steps, hgs_step(rho, c_g, dt,
  * nsub), with HIP events for every depth 1..HGS_TMAX and every tile shape
- * compiled for it, on a temporary context built over the caller's workspace
+ * compiled for it (two passes, the second in reverse order, each candidate
+ * keeping its faster time), on a temporary context built over the caller's workspace
  * (hgs_workspace_bytes(cfg) bytes; its contents are overwritten).
  * Synchronises.
  * *best_tblock receives the fastest depth, *best_tile

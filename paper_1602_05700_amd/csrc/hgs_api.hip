@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hgs.h"
@@ -298,9 +299,8 @@ bool use_vec(const Layout& L) {
     return L.nx % Vec16<S>::N == 0;
 }
 
-// Boundaries whose ghosts follow the interior every substep (one substep per
-// stencil launch, then a ghost launch), as opposed to ghosts frozen over a
-// hydrodynamical step (multipole, user).
+// Boundaries whose ghosts follow the interior every substep, as opposed to
+// ghosts frozen over a hydrodynamical step (multipole, user).
 bool local_bc(int bc) { return bc == HGS_BC_ROBIN || bc == HGS_BC_OUTGOING || bc == HGS_BC_PERIODIC; }
 
 // Substeps per launch: the fused depth, except for grids with a local
@@ -398,13 +398,13 @@ LocalGeom local_geom(const hgs_ctx* c) {
     return LocalGeom{c->cfg.x0, c->cfg.y0, c->cfg.z0, c->cfg.dx, c->cfg.origin[0], c->cfg.origin[1], c->cfg.origin[2]};
 }
 
-// New level's ghosts from its interior (cur = the previous level for the
-// outgoing rule; nullptr = each rule's steady form).
+// Ghosts of buffer nxt from its interior: the periodic copy, else Robin's
+// relation (the outgoing rule's steady form).
 template <typename S>
-void run_local_ghosts(hgs_ctx* c, int nxt, int cur, double c_dt) {
+void run_local_ghosts(hgs_ctx* c, int nxt) {
     const int maxfast = std::max(c->L.nx, c->L.ny), maxslow = std::max(c->L.ny, c->L.nz);
     hipLaunchKernelGGL(k_local_ghosts<S>, dim3((maxfast + 255) / 256, maxslow, 6), dim3(256), 0, c->stream, c->L,
-                       local_geom(c), c->cfg.bc, B<S>(c, nxt), cur >= 0 ? (const S*)B<S>(c, cur) : nullptr, c_dt);
+                       local_geom(c), c->cfg.bc, B<S>(c, nxt));
 }
 
 // Domain-mean density into c->mean (FP64; fixed-order partial sums).
@@ -420,7 +420,6 @@ void run_mean(hgs_ctx* c, const void* rho) {
 template <typename S>
 void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, double c_dt) {
     const S* r = static_cast<const S*>(rho);
-    const bool local = local_bc(c->cfg.bc);
     const double* rbar = c->cfg.bc == HGS_BC_PERIODIC ? c->mean : nullptr;
     const int T = fused_depth(c);
     const int mode = c->cfg.bc == HGS_BC_ROBIN      ? TB_ROBIN
@@ -449,7 +448,7 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
             // writes its new level over them and sets them again); Robin
             // ghosts are set once at the end; the fused outgoing launch stores
             // its ghosts itself
-            if (mode == TB_PERIODIC) run_local_ghosts<S>(c, o0, -1, c_dt);
+            if (mode == TB_PERIODIC) run_local_ghosts<S>(c, o0);
             c->cur = o0;
             c->old = o1;
             nsub -= T;
@@ -457,36 +456,45 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
             int zc, tx, ty, nb;
             Timed tm(c, HGS_KERNEL_STENCIL);
             const LocalGeom lg = local_geom(c);
+            const S* a = B<S>(c, c->cur);
+            S* o = B<S>(c, c->old);
             if (use_vec<S>(c->L)) {
                 stream_dims(c->L, 64 * Vec16<S>::N, zc, tx, ty, nb);
                 if (mode == TB_ROBIN)
-                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY, true>), dim3(nb), dim3(64, SBY), 0, c->stream,
-                                       B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
+                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY, ST_ROBIN>), dim3(nb), dim3(64, SBY), 0, c->stream,
+                                       a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
+                else if (mode == TB_OUTGOING)
+                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY, ST_OUTGOING>), dim3(nb), dim3(64, SBY), 0,
+                                       c->stream, a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
                 else
-                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream,
-                                       B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
+                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream, a, o, r,
+                                       c->L, sc, zc, tx, ty, rbar, lg, c_dt);
             } else {
                 stream_dims(c->L, SBX, zc, tx, ty, nb);
                 if (mode == TB_ROBIN)
-                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY, true>), dim3(nb), dim3(SBX, SBY), 0,
-                                       c->stream, B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
+                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY, ST_ROBIN>), dim3(nb), dim3(SBX, SBY), 0,
+                                       c->stream, a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
+                else if (mode == TB_OUTGOING)
+                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY, ST_OUTGOING>), dim3(nb), dim3(SBX, SBY), 0,
+                                       c->stream, a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
                 else
-                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream,
-                                       B<S>(c, c->cur), B<S>(c, c->old), r, c->L, sc, zc, tx, ty, rbar, lg);
+                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream, a, o,
+                                       r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
             }
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(4.0 * sizeof(S) * cells, cells);
-            // the new level (written over phi^{n-1}) gets its ghosts from its
-            // interior and, for the outgoing rule, from phi^n (Robin substeps
-            // evaluate their ghosts where they read them: set at the end)
-            if (local && mode != TB_ROBIN) run_local_ghosts<S>(c, c->old, c->cur, c_dt);
+            // the new level (written over phi^{n-1}) gets its periodic ghosts
+            // from its interior (Robin substeps evaluate their ghosts where
+            // they read them, set at the end; outgoing substeps store the new
+            // level's ghosts themselves)
+            if (mode == TB_PERIODIC) run_local_ghosts<S>(c, c->old);
             std::swap(c->cur, c->old);
             nsub -= 1;
         }
     }
     // Robin: the substeps evaluate their ghosts where they read them; phi^n's
     // ghost layer is set once, for the gradient, the residual and the faces
-    if (mode == TB_ROBIN) run_local_ghosts<S>(c, c->cur, -1, c_dt);
+    if (mode == TB_ROBIN) run_local_ghosts<S>(c, c->cur);
 }
 
 // Gradient over the cells of layout W read from phi (W may be a box inside
@@ -558,8 +566,8 @@ void run_set_state(hgs_ctx* c, const void* phi, const void* phidot, double dt) {
     hipLaunchKernelGGL(k_set_state<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream, B<S>(c, c->cur),
                        B<S>(c, c->old), static_cast<const S*>(phi), static_cast<const S*>(phidot), dt, c->L);
     if (local_bc(c->cfg.bc)) {
-        run_local_ghosts<S>(c, c->cur, -1, 0.0);
-        run_local_ghosts<S>(c, c->old, -1, 0.0);
+        run_local_ghosts<S>(c, c->cur);
+        run_local_ghosts<S>(c, c->old);
     }
 }
 
@@ -626,8 +634,8 @@ void run_raw_in(hgs_ctx* c, const void* a, const void* b) {
     hipLaunchKernelGGL(k_interior_in<S>, dim3(grid_for(ncell(c))), dim3(256), 0, c->stream,
                        static_cast<const S*>(b), c->L, B<S>(c, c->old));
     if (local_bc(c->cfg.bc)) {
-        run_local_ghosts<S>(c, c->cur, -1, 0.0);
-        run_local_ghosts<S>(c, c->old, -1, 0.0);
+        run_local_ghosts<S>(c, c->cur);
+        run_local_ghosts<S>(c, c->old);
     }
 }
 
@@ -1857,18 +1865,22 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
         return fail(nullptr, HGS_ERR_DEVICE, "hgs_autotune: event creation failed");
     }
     const int reps = 3;
-    double best_ms = -1.0;
-    int best = 1, best_t = 0;
-    hgs_status st = HGS_OK;
     // every depth 1..HGS_TMAX, and every tile shape compiled for a depth; a
     // depth whose fused launch nsub never reaches (T > nsub) is timed as well,
-    // it then runs streaming substeps only
-    for (int t = 1; t <= HGS_TMAX && st == HGS_OK; ++t) {
-        const int ntile = t >= 2 ? tile_count(t) : 1;
-        double best_here = -1.0;
-        for (int tile = 0; tile < ntile && st == HGS_OK; ++tile) {
-            c->tblock = t;
-            c->tile = tile;
+    // it then runs streaming substeps only.  Two passes, the second in reverse
+    // order, each candidate keeping its faster one: launches right after an
+    // idle gap run slower for a while, which would otherwise count against
+    // whichever candidate comes first.
+    std::vector<std::pair<int, int>> cand;
+    for (int t = 1; t <= HGS_TMAX; ++t)
+        for (int tile = 0; tile < (t >= 2 ? tile_count(t) : 1); ++tile) cand.emplace_back(t, tile);
+    std::vector<double> per_cand(cand.size(), -1.0);
+    hgs_status st = HGS_OK;
+    for (int pass = 0; pass < 2 && st == HGS_OK; ++pass) {
+        for (size_t q = 0; q < cand.size() && st == HGS_OK; ++q) {
+            const size_t i = pass == 0 ? q : cand.size() - 1 - q;
+            c->tblock = cand[i].first;
+            c->tile = cand[i].second;
             st = hgs_step(c, rho, c_g, dt, nsub);  // warm-up
             if (st != HGS_OK) break;
             (void)hipEventRecord(e0, c->stream);
@@ -1881,14 +1893,22 @@ extern "C" hgs_status hgs_autotune(const hgs_config* cfg, const void* rho, doubl
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
             const double per = (double)ms / (reps * nsub);
-            if (best_here < 0.0 || per < best_here) best_here = per;
-            if (best_ms < 0.0 || per < best_ms) {
-                best_ms = per;
-                best = t;
-                best_t = tile;
-            }
+            if (per_cand[i] < 0.0 || per < per_cand[i]) per_cand[i] = per;
         }
-        if (ms_per_substep) ms_per_substep[t - 1] = best_here;
+    }
+    double best_ms = -1.0;
+    int best = 1, best_t = 0;
+    if (ms_per_substep)
+        for (int i = 0; i < HGS_TMAX; ++i) ms_per_substep[i] = -1.0;
+    for (size_t i = 0; i < cand.size() && st == HGS_OK; ++i) {
+        const int t = cand[i].first;
+        if (ms_per_substep && (ms_per_substep[t - 1] < 0.0 || per_cand[i] < ms_per_substep[t - 1]))
+            ms_per_substep[t - 1] = per_cand[i];
+        if (best_ms < 0.0 || per_cand[i] < best_ms) {
+            best_ms = per_cand[i];
+            best = t;
+            best_t = cand[i].second;
+        }
     }
     if (st != HGS_OK && c) g_err = c->err;
     (void)hipEventDestroy(e0);

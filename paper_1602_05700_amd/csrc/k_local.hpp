@@ -23,12 +23,14 @@ namespace hgs {
 
 // One thread per face ghost; grid (ceil(max(nx, ny) / 256), max(ny, nz), 6),
 // face f = blockIdx.z in the order x-, x+, y-, y+, z-, z+.  In-face index
-// (a, b): x faces (j, k), y faces (i, k), z faces (i, j).  nxt holds the new
-// level's interior; cur (the previous level with its ghosts) is read by the
-// outgoing rule only, and cur == nullptr applies each rule's steady form.
+// (a, b): x faces (j, k), y faces (i, k), z faces (i, j).  The ghosts of nxt
+// from its interior: the periodic copy, else Robin's relation (the Robin rule,
+// and the steady form of the outgoing one, which the state set-up uses).  The
+// substeps themselves evaluate (Robin) or advance (outgoing) the ghosts they
+// need: outgoing_ghost and robin_ghost, with these operands, in the stencil
+// kernels.
 template <typename S>
-__global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int bc, S* __restrict__ nxt,
-                                                      const S* __restrict__ cur, double c_dt) {
+__global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int bc, S* __restrict__ nxt) {
     const int f = blockIdx.z, axis = f >> 1, hi = f & 1;
     const int a = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
     const int na = axis == 0 ? L.ny : L.nx, nb = axis == 2 ? L.ny : L.nz;
@@ -48,31 +50,13 @@ __global__ __launch_bounds__(256) void k_local_ghosts(Layout L, LocalGeom g, int
         nxt[pg] = nxt[L.idx(op[0], op[1], op[2])];
         return;
     }
-    if (bc == HGS_BC_ROBIN || cur == nullptr) {
-        // Robin (and the steady form of the outgoing rule)
-        const S ci[3] = {local_coord<S>(g.x0, g.ox, g.dx, in[0]), local_coord<S>(g.y0, g.oy, g.dx, in[1]),
-                         local_coord<S>(g.z0, g.oz, g.dx, in[2])};
-        S cg[3] = {ci[0], ci[1], ci[2]};
-        cg[axis] = axis == 0   ? local_coord<S>(g.x0, g.ox, g.dx, gh[0])
-                   : axis == 1 ? local_coord<S>(g.y0, g.oy, g.dx, gh[1])
-                               : local_coord<S>(g.z0, g.oz, g.dx, gh[2]);
-        nxt[pg] = robin_ghost(local_r2(ci[0], ci[1], ci[2]), local_r2(cg[0], cg[1], cg[2]), nxt[pi]);
-        return;
-    }
-    // outgoing (outgoing_ghost): positions of the ghost, the neighbour and
-    // their midpoint (the face plane along the axis)
-    const double lo[3] = {g.x0, g.y0, g.z0}, oc[3] = {g.ox, g.oy, g.oz};
-    S ci[3], cg[3], cf[3];
-    for (int d = 0; d < 3; ++d) {
-        ci[d] = local_coord<S>(lo[d], oc[d], g.dx, in[d]);
-        cg[d] = ci[d];
-        cf[d] = ci[d];
-    }
-    cg[axis] = local_coord<S>(lo[axis], oc[axis], g.dx, gh[axis]);
-    cf[axis] = local_face<S>(lo[axis], oc[axis], g.dx, hi ? n[axis] : 0);
-    const S s = hi ? cf[axis] : -cf[axis];
-    nxt[pg] = outgoing_ghost(local_r2(ci[0], ci[1], ci[2]), local_r2(cg[0], cg[1], cg[2]),
-                             local_r2(cf[0], cf[1], cf[2]), s, (S)(c_dt / g.dx), cur[pg], cur[pi], nxt[pi]);
+    const S ci[3] = {local_coord<S>(g.x0, g.ox, g.dx, in[0]), local_coord<S>(g.y0, g.oy, g.dx, in[1]),
+                     local_coord<S>(g.z0, g.oz, g.dx, in[2])};
+    S cg[3] = {ci[0], ci[1], ci[2]};
+    cg[axis] = axis == 0   ? local_coord<S>(g.x0, g.ox, g.dx, gh[0])
+               : axis == 1 ? local_coord<S>(g.y0, g.oy, g.dx, gh[1])
+                           : local_coord<S>(g.z0, g.oz, g.dx, gh[2]);
+    nxt[pg] = robin_ghost(local_r2(ci[0], ci[1], ci[2]), local_r2(cg[0], cg[1], cg[2]), nxt[pi]);
 }
 
 // Block-wide FP64 sum over 256 threads in a fixed order (wave butterflies,

@@ -13,6 +13,27 @@
 
 namespace hgs {
 
+// Outer-boundary forms of the streaming substep:
+//   ST_PLAIN     ghosts read from the ghost layer (frozen ghosts, or ghosts a
+//                launch after the substep sets);
+//   ST_ROBIN     face cells evaluate their Robin ghosts where they read them
+//                (robin_beside), so no ghost launch is needed between substeps;
+//   ST_OUTGOING  face cells read the old ghost from the ghost layer and store
+//                the new level's ghost beside their own new value (the
+//                outgoing rule needs nothing else: its old ghost, the cell's
+//                old and new values), so no ghost launch follows the substep.
+constexpr int ST_PLAIN = 0, ST_ROBIN = 1, ST_OUTGOING = 2;
+
+// The new level's outgoing ghost beside a face cell: g0 the old ghost, i0 and
+// i1 the cell's old and new values; (x, y, z) the cell, (gx, gy, gz) the
+// ghost and (fx, fy, fz) the face point between them, s the face's signed
+// normal coordinate: the operands of the ghost launch, the same bits.
+template <typename S>
+__device__ __forceinline__ S outgoing_beside(S x, S y, S z, S gx, S gy, S gz, S fx, S fy, S fz, S s, S kk, S g0,
+                                             S i0, S i1) {
+    return outgoing_ghost(local_r2(x, y, z), local_r2(gx, gy, gz), local_r2(fx, fy, fz), s, kk, g0, i0, i1);
+}
+
 // The Robin ghost beside a face cell, evaluated where it is read: the rule's
 // value from the cell's own value v, with the ghost at the cell's position
 // moved past the face, (gx, gy, gz).  These are the operands the ghost launch
@@ -25,14 +46,15 @@ __device__ __forceinline__ S robin_beside(S x, S y, S z, S gx, S gy, S gz, S v) 
 
 // rbar (nullable, device): density subtracted from rho in the source, the
 // domain mean on a periodic grid; rho - 0 = rho exactly, so results without it
-// are bit-identical to the fused kernels.  ROBIN: the face cells evaluate
-// their Robin ghosts (robin_beside; lg: cell positions) instead of reading
-// the ghost layer.
-template <typename S, int BX, int BY, bool ROBIN = false>
+// are bit-identical to the fused kernels.  BND: ST_PLAIN, ST_ROBIN or
+// ST_OUTGOING (above; lg: cell positions, c_dt = c_g dt).
+template <typename S, int BX, int BY, int BND = ST_PLAIN>
 __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict__ cur, S* __restrict__ old_new,
                                                             const S* __restrict__ rho, Layout L, StepCoef c,
                                                             int zc, int tiles_x, int tiles_y,
-                                                            const double* __restrict__ rbar, LocalGeom lg) {
+                                                            const double* __restrict__ rbar, LocalGeom lg,
+                                                            double c_dt) {
+    constexpr bool ROBIN = BND == ST_ROBIN;
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = bid % tiles_x;
     const int ty = (bid / tiles_x) % tiles_y;
@@ -69,7 +91,43 @@ __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict_
         }
         const S o = *po;
         const S r = source(*pr, rb);
-        *po = (S)update(c, z0, xm, xp, ym, yp, zmu, zpu, o, r);
+        const S nv = (S)update(c, z0, xm, xp, ym, yp, zmu, zpu, o, r);
+        *po = nv;
+        if (BND == ST_OUTGOING && (i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1 || k == 0 || k == L.nz - 1)) {
+            const S kk = (S)(c_dt / lg.dx);
+            const S cx = local_coord<S>(lg.x0, lg.ox, lg.dx, i), cy = local_coord<S>(lg.y0, lg.oy, lg.dx, j),
+                    cz = local_coord<S>(lg.z0, lg.oz, lg.dx, k);
+            if (i == 0) {
+                const S f = local_face<S>(lg.x0, lg.ox, lg.dx, 0);
+                po[-1] = outgoing_beside(cx, cy, cz, local_coord<S>(lg.x0, lg.ox, lg.dx, -1), cy, cz, f, cy, cz, -f, kk,
+                                         xm, z0, nv);
+            }
+            if (i == L.nx - 1) {
+                const S f = local_face<S>(lg.x0, lg.ox, lg.dx, L.nx);
+                po[1] = outgoing_beside(cx, cy, cz, local_coord<S>(lg.x0, lg.ox, lg.dx, L.nx), cy, cz, f, cy, cz, f, kk,
+                                        xp, z0, nv);
+            }
+            if (j == 0) {
+                const S f = local_face<S>(lg.y0, lg.oy, lg.dx, 0);
+                po[-pitch] = outgoing_beside(cx, cy, cz, cx, local_coord<S>(lg.y0, lg.oy, lg.dx, -1), cz, cx, f, cz, -f,
+                                             kk, ym, z0, nv);
+            }
+            if (j == L.ny - 1) {
+                const S f = local_face<S>(lg.y0, lg.oy, lg.dx, L.ny);
+                po[pitch] = outgoing_beside(cx, cy, cz, cx, local_coord<S>(lg.y0, lg.oy, lg.dx, L.ny), cz, cx, f, cz, f,
+                                            kk, yp, z0, nv);
+            }
+            if (k == 0) {
+                const S f = local_face<S>(lg.z0, lg.oz, lg.dx, 0);
+                po[-plane] = outgoing_beside(cx, cy, cz, cx, cy, local_coord<S>(lg.z0, lg.oz, lg.dx, -1), cx, cy, f, -f,
+                                             kk, zm, z0, nv);
+            }
+            if (k == L.nz - 1) {
+                const S f = local_face<S>(lg.z0, lg.oz, lg.dx, L.nz);
+                po[plane] = outgoing_beside(cx, cy, cz, cx, cy, local_coord<S>(lg.z0, lg.oz, lg.dx, L.nz), cx, cy, f, f,
+                                            kk, zp, z0, nv);
+            }
+        }
         zm = z0;
         z0 = zp;
         pc += plane;
@@ -191,12 +249,69 @@ __device__ __forceinline__ VLane vlane(const Layout& L, int tx, int ty, int BY) 
     return v;
 }
 
+// ST_OUTGOING ghosts of a vectorised lane at the faces it touches: the x
+// ghost beside its first / last cell (old ghost: the lane's left / right
+// neighbour, loaded from the ghost layer), the y ghost row beside a face row
+// and the z ghost plane beside a face plane (old ghosts: the loaded ym, yp,
+// zm, zp vectors); new values stored into the new level's ghost layer.
+template <typename S>
+__device__ __forceinline__ void stream_v_outgoing(const Layout& L, const LocalGeom& lg, double c_dt, const VLane& g,
+                                               int k, S* po, int pitch, int64_t plane, const typename Vec16<S>::T& z0,
+                                               const typename Vec16<S>::T& out, S left, S right,
+                                               const typename Vec16<S>::T& ym, const typename Vec16<S>::T& yp,
+                                               const typename Vec16<S>::T& zm, const typename Vec16<S>::T& zp) {
+    using V = Vec16<S>;
+    using VT = typename V::T;
+    constexpr int N = V::N;
+    const S kk = (S)(c_dt / lg.dx);
+    const S cy = local_coord<S>(lg.y0, lg.oy, lg.dx, g.j), cz = local_coord<S>(lg.z0, lg.oz, lg.dx, k);
+    if (g.i0 == 0) {
+        const S cx = local_coord<S>(lg.x0, lg.ox, lg.dx, 0), f = local_face<S>(lg.x0, lg.ox, lg.dx, 0);
+        po[-1] = outgoing_beside(cx, cy, cz, local_coord<S>(lg.x0, lg.ox, lg.dx, -1), cy, cz, f, cy, cz, -f, kk, left,
+                                 (S)V::get(z0, 0), (S)V::get(out, 0));
+    }
+    if (g.i0 + N == L.nx) {
+        const S cx = local_coord<S>(lg.x0, lg.ox, lg.dx, L.nx - 1), f = local_face<S>(lg.x0, lg.ox, lg.dx, L.nx);
+        po[N] = outgoing_beside(cx, cy, cz, local_coord<S>(lg.x0, lg.ox, lg.dx, L.nx), cy, cz, f, cy, cz, f, kk, right,
+                                (S)V::get(z0, N - 1), (S)V::get(out, N - 1));
+    }
+    // y and z ghost rows / planes: one vector per face
+    for (int face = 0; face < 4; ++face) {
+        const bool on = face == 0 ? g.j == 0 : face == 1 ? g.j == L.ny - 1 : face == 2 ? k == 0 : k == L.nz - 1;
+        if (!on) continue;
+        const bool hi = face & 1;
+        const VT& gold = face == 0 ? ym : face == 1 ? yp : face == 2 ? zm : zp;
+        S gc, fc;  // ghost and face coordinate along the normal
+        if (face < 2) {
+            gc = local_coord<S>(lg.y0, lg.oy, lg.dx, hi ? L.ny : -1);
+            fc = local_face<S>(lg.y0, lg.oy, lg.dx, hi ? L.ny : 0);
+        } else {
+            gc = local_coord<S>(lg.z0, lg.oz, lg.dx, hi ? L.nz : -1);
+            fc = local_face<S>(lg.z0, lg.oz, lg.dx, hi ? L.nz : 0);
+        }
+        VT gnew;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const S cx = local_coord<S>(lg.x0, lg.ox, lg.dx, g.i0 + n);
+            const S v = face < 2 ? outgoing_beside(cx, cy, cz, cx, gc, cz, cx, fc, cz, hi ? fc : -fc, kk,
+                                                   (S)V::get(gold, n), (S)V::get(z0, n), (S)V::get(out, n))
+                                 : outgoing_beside(cx, cy, cz, cx, cy, gc, cx, cy, fc, hi ? fc : -fc, kk,
+                                                   (S)V::get(gold, n), (S)V::get(z0, n), (S)V::get(out, n));
+            V::set(gnew, n, v);
+        }
+        const int64_t off = face == 0 ? -(int64_t)pitch : face == 1 ? (int64_t)pitch : face == 2 ? -plane : plane;
+        *reinterpret_cast<VT*>(po + off) = gnew;
+    }
+}
+
 // One (64N x BY) column tile, planes [k0, k1): the body shared by the
-// single-grid and the batched launches.  ROBIN as in k_leapfrog_stream.
-template <typename S, int BY, bool ROBIN = false>
+// single-grid and the batched launches.  BND as in k_leapfrog_stream.
+template <typename S, int BY, int BND = ST_PLAIN>
 __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __restrict__ old_new,
                                               const S* __restrict__ rho, const Layout& L, const StepCoef& c, int tx,
-                                              int ty, int k0, int k1, double rb, const LocalGeom& lg = LocalGeom{}) {
+                                              int ty, int k0, int k1, double rb, const LocalGeom& lg = LocalGeom{},
+                                              double c_dt = 0.0) {
+    constexpr bool ROBIN = BND == ST_ROBIN;
     using V = Vec16<S>;
     using VT = typename V::T;
     constexpr int N = V::N;
@@ -254,6 +369,9 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
             V::set(out, n, v);
         }
         if (g.active) *reinterpret_cast<VT*>(po) = out;
+        if (BND == ST_OUTGOING && g.active &&
+            (g.i0 == 0 || g.i0 + N == L.nx || g.j == 0 || g.j == L.ny - 1 || k == 0 || k == L.nz - 1))
+            stream_v_outgoing<S>(L, lg, c_dt, g, k, po, pitch, plane, z0, out, left, right, ym, yp, zm, zp);
         zm = z0;
         z0 = zp;
         pc += plane;
@@ -262,17 +380,19 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
     }
 }
 
-template <typename S, int BY, bool ROBIN = false>
+template <typename S, int BY, int BND = ST_PLAIN>
 __global__ __launch_bounds__(64 * BY) void k_leapfrog_stream_v(const S* __restrict__ cur, S* __restrict__ old_new,
                                                                const S* __restrict__ rho, Layout L, StepCoef c, int zc,
                                                                int tiles_x, int tiles_y,
-                                                               const double* __restrict__ rbar, LocalGeom lg) {
+                                                               const double* __restrict__ rbar, LocalGeom lg,
+                                                               double c_dt) {
     const int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = bid % tiles_x;
     const int ty = (bid / tiles_x) % tiles_y;
     const int tz = bid / (tiles_x * tiles_y);
     const int k0 = tz * zc;
-    stream_v_tile<S, BY, ROBIN>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz), rbar ? *rbar : 0.0, lg);
+    stream_v_tile<S, BY, BND>(cur, old_new, rho, L, c, tx, ty, k0, min(k0 + zc, L.nz), rbar ? *rbar : 0.0, lg,
+                              c_dt);
 }
 
 // Central-difference gradient, 16 bytes per lane along x, R rows per thread:
