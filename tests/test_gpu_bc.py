@@ -184,10 +184,13 @@ def test_fused_local_bc_bitwise_equals_streaming(gpu_lib, bc, storage, shape, T,
     assert all(torch.equal(u, v) for u, v in zip(a.accel(), b.accel()))
 
 
+@pytest.mark.parametrize("tblock", [1, 4])
 @pytest.mark.parametrize("bc", LOCAL)
-def test_fused_local_bc_against_oracle_256(gpu_lib, bc):
-    """At 256^3 FP32 (fused depth 4, the launch the bench times for these
-    boundaries) two hydro steps against the FP64 oracle at the FP32 bar."""
+def test_fused_local_bc_against_oracle_256(gpu_lib, bc, tblock):
+    """At 256^3 FP32, fused depth 4 and one substep per launch (the two forms
+    the bench times for these boundaries, the latter with its ghosts
+    evaluated or advanced inside the substep), two hydro steps against the
+    FP64 oracle at the FP32 bar."""
     import torch
 
     import workloads
@@ -198,7 +201,7 @@ def test_fused_local_bc_against_oracle_256(gpu_lib, bc):
     rho = workloads.blob_density_torch(n, workloads.blob_params(0, 8), "cuda", torch.float32)
     r64 = rho.double().cpu().numpy()
     origin = (0.03, -0.02, 0.01)
-    s = gpu_lib.Solver(n, storage="f32", eta=0.5, bc=bc, origin=origin, tblock=4)
+    s = gpu_lib.Solver(n, storage="f32", eta=0.5, bc=bc, origin=origin, tblock=tblock)
     o = Oracle(g, eta=0.5, bc=bc, origin=origin)
     for _ in range(2):
         s.step(rho, 1.0, 0.4 * g.dx, 4)
