@@ -161,7 +161,7 @@ __device__ __forceinline__ S local_face(double lo, double o, double dx, int i) {
 // (1 - al) u_i'] / (1 + al) with u = r phi, divided by r_g).  In the storage
 // type: FP64 with correctly rounded divides and square roots, FP32 with the
 // hardware reciprocal and reciprocal square root.  One function for the
-// ghost launch and the fused launch, so both give the same bits.
+// streaming and the fused substeps, so both give the same bits.
 __device__ __forceinline__ double outgoing_ghost(double ri2, double rg2, double rf2, double s, double kk,
                                                  double g0, double i0, double i1) {
     const double b = sqrt(ri2 / rg2);

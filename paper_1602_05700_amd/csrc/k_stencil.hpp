@@ -27,7 +27,7 @@ constexpr int ST_PLAIN = 0, ST_ROBIN = 1, ST_OUTGOING = 2;
 // The new level's outgoing ghost beside a face cell: g0 the old ghost, i0 and
 // i1 the cell's old and new values; (x, y, z) the cell, (gx, gy, gz) the
 // ghost and (fx, fy, fz) the face point between them, s the face's signed
-// normal coordinate: the operands of the ghost launch, the same bits.
+// normal coordinate: the operands the fused launch uses, the same bits.
 template <typename S>
 __device__ __forceinline__ S outgoing_beside(S x, S y, S z, S gx, S gy, S gz, S fx, S fy, S fz, S s, S kk, S g0,
                                              S i0, S i1) {
