@@ -466,6 +466,9 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
                 else if (mode == TB_OUTGOING)
                     hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY, ST_OUTGOING>), dim3(nb), dim3(64, SBY), 0,
                                        c->stream, a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
+                else if (mode == TB_PERIODIC)
+                    hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY, ST_PERIODIC>), dim3(nb), dim3(64, SBY), 0,
+                                       c->stream, a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
                 else
                     hipLaunchKernelGGL((k_leapfrog_stream_v<S, SBY>), dim3(nb), dim3(64, SBY), 0, c->stream, a, o, r,
                                        c->L, sc, zc, tx, ty, rbar, lg, c_dt);
@@ -477,17 +480,18 @@ void run_substeps(hgs_ctx* c, const void* rho, const StepCoef& sc, int nsub, dou
                 else if (mode == TB_OUTGOING)
                     hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY, ST_OUTGOING>), dim3(nb), dim3(SBX, SBY), 0,
                                        c->stream, a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
+                else if (mode == TB_PERIODIC)
+                    hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY, ST_PERIODIC>), dim3(nb), dim3(SBX, SBY), 0,
+                                       c->stream, a, o, r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
                 else
                     hipLaunchKernelGGL((k_leapfrog_stream<S, SBX, SBY>), dim3(nb), dim3(SBX, SBY), 0, c->stream, a, o,
                                        r, c->L, sc, zc, tx, ty, rbar, lg, c_dt);
             }
             const double cells = (double)c->L.nx * c->L.ny * c->L.nz;
             tm.end(4.0 * sizeof(S) * cells, cells);
-            // the new level (written over phi^{n-1}) gets its periodic ghosts
-            // from its interior (Robin substeps evaluate their ghosts where
-            // they read them, set at the end; outgoing substeps store the new
-            // level's ghosts themselves)
-            if (mode == TB_PERIODIC) run_local_ghosts<S>(c, c->old);
+            // no ghost launch: Robin substeps evaluate their ghosts where they
+            // read them (set at the end), outgoing and periodic substeps store
+            // the new level's ghosts themselves
             std::swap(c->cur, c->old);
             nsub -= 1;
         }

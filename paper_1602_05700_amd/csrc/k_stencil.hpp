@@ -21,8 +21,11 @@ namespace hgs {
 //   ST_OUTGOING  face cells read the old ghost from the ghost layer and store
 //                the new level's ghost beside their own new value (the
 //                outgoing rule needs nothing else: its old ghost, the cell's
-//                old and new values), so no ghost launch follows the substep.
-constexpr int ST_PLAIN = 0, ST_ROBIN = 1, ST_OUTGOING = 2;
+//                old and new values), so no ghost launch follows the substep;
+//   ST_PERIODIC  face cells store their new value also into the ghost across
+//                the opposite face, whose periodic image they are, so no
+//                ghost launch follows the substep.
+constexpr int ST_PLAIN = 0, ST_ROBIN = 1, ST_OUTGOING = 2, ST_PERIODIC = 3;
 
 // The new level's outgoing ghost beside a face cell: g0 the old ghost, i0 and
 // i1 the cell's old and new values; (x, y, z) the cell, (gx, gy, gz) the
@@ -93,6 +96,14 @@ __global__ __launch_bounds__(BX* BY) void k_leapfrog_stream(const S* __restrict_
         const S r = source(*pr, rb);
         const S nv = (S)update(c, z0, xm, xp, ym, yp, zmu, zpu, o, r);
         *po = nv;
+        if (BND == ST_PERIODIC) {
+            if (i == 0) po[L.nx] = nv;  // the ghost x = nx
+            if (i == L.nx - 1) po[-L.nx] = nv;  // the ghost x = -1
+            if (j == 0) po[(int64_t)L.ny * pitch] = nv;
+            if (j == L.ny - 1) po[-(int64_t)L.ny * pitch] = nv;
+            if (k == 0) po[(int64_t)L.nz * plane] = nv;
+            if (k == L.nz - 1) po[-(int64_t)L.nz * plane] = nv;
+        }
         if (BND == ST_OUTGOING && (i == 0 || i == L.nx - 1 || j == 0 || j == L.ny - 1 || k == 0 || k == L.nz - 1)) {
             const S kk = (S)(c_dt / lg.dx);
             const S cx = local_coord<S>(lg.x0, lg.ox, lg.dx, i), cy = local_coord<S>(lg.y0, lg.oy, lg.dx, j),
@@ -369,6 +380,16 @@ __device__ __forceinline__ void stream_v_tile(const S* __restrict__ cur, S* __re
             V::set(out, n, v);
         }
         if (g.active) *reinterpret_cast<VT*>(po) = out;
+        if (BND == ST_PERIODIC && g.active) {
+            // the periodic images: x ghosts from the first / last cell of the
+            // row, y ghost rows and z ghost planes from whole vectors
+            if (g.i0 == 0) po[L.nx] = (S)V::get(out, 0);
+            if (g.i0 + N == L.nx) po[N - 1 - L.nx] = (S)V::get(out, N - 1);
+            if (g.j == 0) *reinterpret_cast<VT*>(po + (int64_t)L.ny * pitch) = out;
+            if (g.j == L.ny - 1) *reinterpret_cast<VT*>(po - (int64_t)L.ny * pitch) = out;
+            if (k == 0) *reinterpret_cast<VT*>(po + (int64_t)L.nz * plane) = out;
+            if (k == L.nz - 1) *reinterpret_cast<VT*>(po - (int64_t)L.nz * plane) = out;
+        }
         if (BND == ST_OUTGOING && g.active &&
             (g.i0 == 0 || g.i0 + N == L.nx || g.j == 0 || g.j == L.ny - 1 || k == 0 || k == L.nz - 1))
             stream_v_outgoing<S>(L, lg, c_dt, g, k, po, pitch, plane, z0, out, left, right, ym, yp, zm, zp);
